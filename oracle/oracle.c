@@ -1,0 +1,526 @@
+/*
+ * FP64 CPU oracle for the D3Q19 lattice Boltzmann stream-collide update of
+ * Bauer & Ruede, "An improved lattice Boltzmann D3Q19 method based on an
+ * alternative equilibrium discretization" (arXiv:1803.04937).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header, table or constant with the GPU library: every constant below is
+ * written out here from the paper.
+ *
+ * Layout of every PDF array: dense structure of arrays, f[q * ncells + cell],
+ * cell = (z * ny + y) * nx + x (x fastest).  All arithmetic is FP64.
+ *
+ * What each function follows:
+ *   velocity set, weights ........ Sec. 2.3 (D3Q19 stencil and weights)
+ *   standard equilibrium ......... Sec. 2.2, eq. discreteEquilibriumStandard,
+ *                                  second-order part, rho0 from Sec. 2.3
+ *   improved equilibrium ......... Sec. 3.2, eq. new_d3q19_equilibrium
+ *   forcing term ................. Sec. 2.3, F_q = w_q / c_s^2 c_q . a
+ *   SRT update ................... Sec. 2.3, eq. lb_srt_with_forces
+ *   macroscopic moments .......... Sec. 2.3, eqs. mass_conservation and
+ *                                  macroscopic_vel_shift
+ *   half-way bounce-back, periodic Sec. 5.1 (duct set-up)
+ *   TRT collision ................ named in Sec. 1 and Sec. 3.3 but not
+ *                                  defined there; the two-relaxation-time
+ *                                  split into even and odd parts over
+ *                                  opposite directions is used, with the
+ *                                  force (odd) relaxed by omega_minus
+ *   adjoint, objectives .......... not in the paper: the exact transpose of
+ *                                  the discrete update above
+ *
+ * Parity pins: the test suite checks these functions against the moment
+ * table of Sec. 3.1 (Table 1), an exact-rational moment-matching
+ * construction from the Maxwellian moments (Sec. 3.1-3.2), streaming against
+ * numpy.roll, conservation of mass and momentum, closed-form shear-wave
+ * decay, the exact plane-Poiseuille solution, the duct projection property
+ * behind Sec. 5.1, and finite differences for the adjoint.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NQ 19
+
+/* ------------------------------------------------------------------------ */
+/* Velocity set (Sec. 2.3).  Order: rest; the six axis directions; the       */
+/* twelve edge directions; opposite directions sit next to each other.       */
+/* ------------------------------------------------------------------------ */
+static const int C[NQ][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+};
+
+/* Weights by the squared length of c_q (Sec. 2.3): 1/3, 1/18, 1/36. */
+static double weight(int q)
+{
+    int n2 = C[q][0] * C[q][0] + C[q][1] * C[q][1] + C[q][2] * C[q][2];
+    if (n2 == 0) return 1.0 / 3.0;
+    if (n2 == 1) return 1.0 / 18.0;
+    return 1.0 / 36.0;
+}
+
+/* The direction with c_p = -c_q, found by search. */
+static int opposite(int q)
+{
+    for (int p = 0; p < NQ; ++p)
+        if (C[p][0] == -C[q][0] && C[p][1] == -C[q][1] && C[p][2] == -C[q][2]) return p;
+    return -1;
+}
+
+typedef struct {
+    int nx, ny, nz;
+    int periodic[3];    /* 1: periodic axis; 0: half-way bounce-back walls   */
+    int improved;       /* 0: D3Q19-S, 1: D3Q19-I                            */
+    int trt;            /* 0: SRT, 1: TRT                                    */
+    int compressible;   /* 0: rho0 = 1 (the paper's choice), 1: rho0 = rho   */
+    double omega;       /* SRT rate, or TRT even rate omega_plus             */
+    double magic;       /* TRT Lambda = (1/w+ - 1/2)(1/w- - 1/2)             */
+    double accel[3];    /* body acceleration a                               */
+} oracle_cfg;
+
+void oracle_velocity_set(int *c_out, double *w_out, int *opp_out)
+{
+    for (int q = 0; q < NQ; ++q) {
+        for (int d = 0; d < 3; ++d) c_out[3 * q + d] = C[q][d];
+        w_out[q] = weight(q);
+        opp_out[q] = opposite(q);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Equilibria, truncated at second order in u.                              */
+/* ------------------------------------------------------------------------ */
+
+/* Standard equilibrium: w rho + w rho0 [3 c_a u_a
+ *                                      + 9/2 u_a u_b (c_a c_b - delta_ab/3)]. */
+static double feq_standard(int q, double rho, double rho0, const double u[3])
+{
+    double first = 0.0, second = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        first += C[q][a] * u[a];
+        for (int b = 0; b < 3; ++b)
+            second += u[a] * u[b] * (C[q][a] * C[q][b] - (a == b ? 1.0 / 3.0 : 0.0));
+    }
+    return weight(q) * rho + weight(q) * rho0 * (3.0 * first + 4.5 * second);
+}
+
+/* Improved equilibrium D3Q19-I, case by case on the type of c_q.  The edge
+ * term -3/2 u_i^2 c_qi^2 is summed over i. */
+static double feq_improved(int q, double rho, double rho0, const double u[3])
+{
+    int n2 = C[q][0] * C[q][0] + C[q][1] * C[q][1] + C[q][2] * C[q][2];
+    double cu = 0.0, uu = 0.0, uc2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        cu += u[i] * C[q][i];
+        uu += u[i] * u[i];
+        uc2 += u[i] * u[i] * C[q][i] * C[q][i];
+    }
+    double bracket;
+    if (n2 == 0)
+        bracket = -uu;
+    else if (n2 == 1)
+        bracket = 3.0 * cu - 3.0 * uu + 6.0 * cu * cu;
+    else
+        bracket = 3.0 * cu - 1.5 * uc2 + 4.5 * cu * cu;
+    return rho * weight(q) + weight(q) * rho0 * bracket;
+}
+
+static double feq(const oracle_cfg *cfg, int q, double rho, double rho0, const double u[3])
+{
+    return cfg->improved ? feq_improved(q, rho, rho0, u) : feq_standard(q, rho, rho0, u);
+}
+
+/* d f^eq_q / d u_b at fixed rho and rho0, differentiated by hand from the two
+ * forms above. */
+static double dfeq_du(const oracle_cfg *cfg, int q, int b, double rho0, const double u[3])
+{
+    double cu = 0.0;
+    for (int i = 0; i < 3; ++i) cu += u[i] * C[q][i];
+    double cb = C[q][b];
+    if (!cfg->improved)
+        return weight(q) * rho0 * (3.0 * cb + 9.0 * cu * cb - 3.0 * u[b]);
+    int n2 = C[q][0] * C[q][0] + C[q][1] * C[q][1] + C[q][2] * C[q][2];
+    if (n2 == 0) return weight(q) * rho0 * (-2.0 * u[b]);
+    if (n2 == 1) return weight(q) * rho0 * (3.0 * cb - 6.0 * u[b] + 12.0 * cu * cb);
+    return weight(q) * rho0 * (3.0 * cb - 3.0 * u[b] * cb * cb + 9.0 * cu * cb);
+}
+
+void oracle_feq(const oracle_cfg *cfg, double rho, double rho0, const double *u, double *out)
+{
+    for (int q = 0; q < NQ; ++q) out[q] = feq(cfg, q, rho, rho0, u);
+}
+
+void oracle_dfeq_du(const oracle_cfg *cfg, double rho0, const double *u, double *out /*[19][3]*/)
+{
+    for (int q = 0; q < NQ; ++q)
+        for (int b = 0; b < 3; ++b) out[3 * q + b] = dfeq_du(cfg, q, b, rho0, u);
+}
+
+/* Forcing term F_q = w_q / c_s^2 (c_q . a), c_s^2 = 1/3. */
+static double force_term(const oracle_cfg *cfg, int q)
+{
+    double ca = 0.0;
+    for (int d = 0; d < 3; ++d) ca += C[q][d] * cfg->accel[d];
+    return weight(q) / (1.0 / 3.0) * ca;
+}
+
+/* TRT odd rate from Lambda = (1/w+ - 1/2)(1/w- - 1/2). */
+static double omega_minus(const oracle_cfg *cfg)
+{
+    if (!cfg->trt) return cfg->omega;
+    double tau_plus = 1.0 / cfg->omega - 0.5;
+    return 1.0 / (0.5 + cfg->magic / tau_plus);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry helpers                                                          */
+/* ------------------------------------------------------------------------ */
+
+static int64_t ncells_of(const oracle_cfg *cfg)
+{
+    return (int64_t)cfg->nx * cfg->ny * cfg->nz;
+}
+
+/* Cell index of x + s*c_q, or -1 if it lies outside a wall axis. */
+static int64_t shifted_cell(const oracle_cfg *cfg, int x, int y, int z, int q, int s)
+{
+    int p[3] = {x + s * C[q][0], y + s * C[q][1], z + s * C[q][2]};
+    int n[3] = {cfg->nx, cfg->ny, cfg->nz};
+    for (int d = 0; d < 3; ++d) {
+        if (p[d] < 0 || p[d] >= n[d]) {
+            if (!cfg->periodic[d]) return -1;
+            p[d] = ((p[d] % n[d]) + n[d]) % n[d];
+        }
+    }
+    return ((int64_t)p[2] * cfg->ny + p[1]) * cfg->nx + p[0];
+}
+
+static int is_solid(const uint8_t *solid, int64_t cell)
+{
+    return cell < 0 || (solid != NULL && solid[cell] != 0);
+}
+
+/* Pull gather with half-way bounce-back: g_q(x) = f_q(x - c_q), or
+ * f_qbar(x) when x - c_q is a wall or a solid cell. */
+static void gather(const oracle_cfg *cfg, const uint8_t *solid, const double *f,
+                   int x, int y, int z, double g[NQ])
+{
+    int64_t n = ncells_of(cfg);
+    int64_t here = ((int64_t)z * cfg->ny + y) * cfg->nx + x;
+    for (int q = 0; q < NQ; ++q) {
+        int64_t src = shifted_cell(cfg, x, y, z, q, -1);
+        if (is_solid(solid, src))
+            g[q] = f[(int64_t)opposite(q) * n + here];
+        else
+            g[q] = f[(int64_t)q * n + src];
+    }
+}
+
+/* rho, and the equilibrium velocity u = (sum_q c_q g_q + a/2) / rho0'. */
+static void macroscopic(const oracle_cfg *cfg, const double g[NQ], double *rho, double *rho0,
+                        double u[3])
+{
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < NQ; ++q) {
+        r += g[q];
+        for (int d = 0; d < 3; ++d) j[d] += C[q][d] * g[q];
+    }
+    *rho = r;
+    *rho0 = cfg->compressible ? r : 1.0;
+    for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * cfg->accel[d]) / *rho0;
+}
+
+/* Collision of one cell: post-collision f* from the gathered g. */
+static void collide(const oracle_cfg *cfg, const double g[NQ], double out[NQ])
+{
+    double rho, rho0, u[3], fe[NQ];
+    macroscopic(cfg, g, &rho, &rho0, u);
+    for (int q = 0; q < NQ; ++q) fe[q] = feq(cfg, q, rho, rho0, u);
+    double w = cfg->omega;
+    if (!cfg->trt) {
+        for (int q = 0; q < NQ; ++q)
+            out[q] = g[q] - w * (g[q] - fe[q]) + (1.0 - w / 2.0) * force_term(cfg, q);
+        return;
+    }
+    double wm = omega_minus(cfg);
+    for (int q = 0; q < NQ; ++q) {
+        int qb = opposite(q);
+        double gp = 0.5 * (g[q] + g[qb]), gm = 0.5 * (g[q] - g[qb]);
+        double ep = 0.5 * (fe[q] + fe[qb]), em = 0.5 * (fe[q] - fe[qb]);
+        out[q] = g[q] - w * (gp - ep) - wm * (gm - em) + (1.0 - wm / 2.0) * force_term(cfg, q);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public forward API                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* f = f^eq(rho_init, u_init) in fluid cells, w_q in solid cells.
+ * u_init is [3][cells]. */
+void oracle_init(const oracle_cfg *cfg, const uint8_t *solid, const double *rho_init,
+                 const double *u_init, double *f)
+{
+    int64_t n = ncells_of(cfg);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        if (solid && solid[c]) {
+            for (int q = 0; q < NQ; ++q) f[q * n + c] = weight(q);
+            continue;
+        }
+        double u[3] = {u_init[c], u_init[n + c], u_init[2 * n + c]};
+        double rho = rho_init ? rho_init[c] : 1.0;
+        double rho0 = cfg->compressible ? rho : 1.0;
+        for (int q = 0; q < NQ; ++q) f[q * n + c] = feq(cfg, q, rho, rho0, u);
+    }
+}
+
+/* One two-grid pull step, fin -> fout.  Solid cells keep their values. */
+void oracle_step(const oracle_cfg *cfg, const uint8_t *solid, const double *fin, double *fout)
+{
+    int64_t n = ncells_of(cfg);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < cfg->nz; ++z)
+        for (int y = 0; y < cfg->ny; ++y)
+            for (int x = 0; x < cfg->nx; ++x) {
+                int64_t c = ((int64_t)z * cfg->ny + y) * cfg->nx + x;
+                if (solid && solid[c]) {
+                    for (int q = 0; q < NQ; ++q) fout[q * n + c] = fin[q * n + c];
+                    continue;
+                }
+                double g[NQ], out[NQ];
+                gather(cfg, solid, fin, x, y, z, g);
+                collide(cfg, g, out);
+                for (int q = 0; q < NQ; ++q) fout[q * n + c] = out[q];
+            }
+}
+
+void oracle_run(const oracle_cfg *cfg, const uint8_t *solid, double *f, double *tmp, int nsteps)
+{
+    int64_t bytes = ncells_of(cfg) * NQ * (int64_t)sizeof(double);
+    for (int s = 0; s < nsteps; ++s) {
+        oracle_step(cfg, solid, f, tmp);
+        memcpy(f, tmp, (size_t)bytes);
+    }
+}
+
+/* Post-step values at selected cells only (for sampled checks on large
+ * grids): out[k * 19 + q] = f*_q at cells[k]. */
+void oracle_step_cells(const oracle_cfg *cfg, const uint8_t *solid, const double *fin,
+                       const int64_t *cells, int64_t ncell_list, double *out)
+{
+    int64_t n = ncells_of(cfg);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < ncell_list; ++k) {
+        int64_t c = cells[k];
+        int x = (int)(c % cfg->nx), y = (int)((c / cfg->nx) % cfg->ny),
+            z = (int)(c / ((int64_t)cfg->nx * cfg->ny));
+        if (solid && solid[c]) {
+            for (int q = 0; q < NQ; ++q) out[k * NQ + q] = fin[q * n + c];
+            continue;
+        }
+        double g[NQ];
+        gather(cfg, solid, fin, x, y, z, g);
+        collide(cfg, g, out + k * NQ);
+    }
+}
+
+/* Density and velocity of a stored post-collision state:
+ * rho = sum f*, u = (sum c f* - a/2) / rho0'.  Solid cells report 0. */
+void oracle_moments(const oracle_cfg *cfg, const uint8_t *solid, const double *f, double *rho,
+                    double *u)
+{
+    int64_t n = ncells_of(cfg);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        if (solid && solid[c]) {
+            rho[c] = 0.0;
+            for (int d = 0; d < 3; ++d) u[d * n + c] = 0.0;
+            continue;
+        }
+        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < NQ; ++q) {
+            r += f[q * n + c];
+            for (int d = 0; d < 3; ++d) j[d] += C[q][d] * f[q * n + c];
+        }
+        double rho0 = cfg->compressible ? r : 1.0;
+        rho[c] = r;
+        for (int d = 0; d < 3; ++d) u[d * n + c] = (j[d] - 0.5 * cfg->accel[d]) / rho0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint (exact transpose of oracle_step); incompressible form only.       */
+/* ------------------------------------------------------------------------ */
+
+/* Full 19x19 Jacobian J[q][r] = d f*_q / d g_r of the collision of one cell,
+ * and the derivatives of f* with respect to omega and a. */
+static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double J[NQ][NQ],
+                               double dw[NQ], double da[NQ][3])
+{
+    double rho, rho0, u[3], fe[NQ], D[NQ][3], dfe_dg[NQ][NQ];
+    macroscopic(cfg, g, &rho, &rho0, u);
+    for (int q = 0; q < NQ; ++q) {
+        fe[q] = feq(cfg, q, rho, rho0, u);
+        for (int b = 0; b < 3; ++b) D[q][b] = dfeq_du(cfg, q, b, rho0, u);
+    }
+    /* With rho0 = 1: d rho / d g_r = 1, d u_b / d g_r = c_rb, d u_b / d a_b = 1/2. */
+    for (int q = 0; q < NQ; ++q)
+        for (int r = 0; r < NQ; ++r) {
+            double v = weight(q);
+            for (int b = 0; b < 3; ++b) v += D[q][b] * C[r][b];
+            dfe_dg[q][r] = v;
+        }
+    double wp = cfg->omega, wm = omega_minus(cfg);
+    /* Relaxation matrix R = wp P+ + wm P-, P+- = (I +- reversal) / 2. */
+    double R[NQ][NQ];
+    for (int q = 0; q < NQ; ++q)
+        for (int s = 0; s < NQ; ++s) {
+            double pp = 0.5 * ((q == s) + (opposite(q) == s));
+            double pm = 0.5 * ((q == s) - (opposite(q) == s));
+            R[q][s] = cfg->trt ? wp * pp + wm * pm : wp * (q == s);
+        }
+    for (int q = 0; q < NQ; ++q)
+        for (int r = 0; r < NQ; ++r) {
+            double v = (q == r) - R[q][r];
+            for (int s = 0; s < NQ; ++s) v += R[q][s] * dfe_dg[s][r];
+            J[q][r] = v;
+        }
+    double fm = cfg->trt ? wm : wp; /* rate multiplying the force */
+    for (int q = 0; q < NQ; ++q) {
+        for (int b = 0; b < 3; ++b) {
+            double v = 0.0;
+            for (int s = 0; s < NQ; ++s) v += R[q][s] * 0.5 * D[s][b];
+            da[q][b] = v + (1.0 - fm / 2.0) * 3.0 * weight(q) * C[q][b];
+        }
+    }
+    /* d f* / d omega.  For TRT, omega_minus follows omega through fixed Lambda. */
+    for (int q = 0; q < NQ; ++q) {
+        int qb = opposite(q);
+        if (!cfg->trt) {
+            dw[q] = -(g[q] - fe[q]) - 0.5 * force_term(cfg, q);
+        } else {
+            double gp = 0.5 * (g[q] + g[qb]), gm = 0.5 * (g[q] - g[qb]);
+            double ep = 0.5 * (fe[q] + fe[qb]), em = 0.5 * (fe[q] - fe[qb]);
+            double d_plus = -(gp - ep);
+            double d_minus = -(gm - em) - 0.5 * force_term(cfg, q);
+            double tau_p = 1.0 / wp - 0.5;
+            double dwm_dwp = -wm * wm * cfg->magic / (tau_p * tau_p * wp * wp);
+            dw[q] = d_plus + d_minus * dwm_dwp;
+        }
+    }
+}
+
+/* lam_prev = (d step / d f_t)^T lam_next.  grad[0] += dJ/domega,
+ * grad[1..3] += dJ/da (the contribution of this step).  Returns -1 for the
+ * compressible form, which has no adjoint here. */
+int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const double *f_t,
+                        const double *lam_next, double *lam_prev, double *grad)
+{
+    if (cfg->compressible) return -1;
+    int64_t n = ncells_of(cfg);
+    double *plane = (double *)calloc((size_t)cfg->nz * 4, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < cfg->nz; ++z) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < cfg->ny; ++y)
+            for (int x = 0; x < cfg->nx; ++x) {
+                int64_t c = ((int64_t)z * cfg->ny + y) * cfg->nx + x;
+                if (solid && solid[c]) {
+                    for (int q = 0; q < NQ; ++q) lam_prev[q * n + c] = lam_next[q * n + c];
+                    continue;
+                }
+                double g[NQ], J[NQ][NQ], dw[NQ], da[NQ][3], lam[NQ];
+                gather(cfg, solid, f_t, x, y, z, g);
+                collision_jacobian(cfg, g, J, dw, da);
+                for (int q = 0; q < NQ; ++q) lam[q] = lam_next[q * n + c];
+                for (int q = 0; q < NQ; ++q) {
+                    acc[0] += lam[q] * dw[q];
+                    for (int b = 0; b < 3; ++b) acc[1 + b] += lam[q] * da[q][b];
+                }
+                /* mu = J^T lam, pushed back along the pull: g_r(x) was read
+                 * from f_r(x - c_r), or from f_rbar(x) at a wall. */
+                for (int r = 0; r < NQ; ++r) {
+                    double mu = 0.0;
+                    for (int q = 0; q < NQ; ++q) mu += J[q][r] * lam[q];
+                    int64_t src = shifted_cell(cfg, x, y, z, r, -1);
+                    if (is_solid(solid, src))
+                        lam_prev[(int64_t)opposite(r) * n + c] = mu;
+                    else
+                        lam_prev[(int64_t)r * n + src] = mu;
+                }
+            }
+        for (int k = 0; k < 4; ++k) plane[4 * z + k] = acc[k];
+    }
+    for (int z = 0; z < cfg->nz; ++z)
+        for (int k = 0; k < 4; ++k) grad[k] += plane[4 * z + k];
+    free(plane);
+    return 0;
+}
+
+/* Objectives of a stored state and their seeds lam_T = dJ / d f.
+ * kind 0: kinetic energy E = 1/2 sum over fluid cells of |u|^2.
+ * kind 1: outlet flux, sum of u_x over fluid cells of the plane x = nx - 1.
+ * u is the stored-state velocity of oracle_moments (rho0 = 1).  dJda gets
+ * the explicit derivative with respect to a (through u = sum c f - a/2). */
+double oracle_objective(const oracle_cfg *cfg, const uint8_t *solid, int kind, const double *f,
+                        double *lam_seed, double *dJda)
+{
+    int64_t n = ncells_of(cfg);
+    double J = 0.0, da[3] = {0.0, 0.0, 0.0};
+    for (int64_t c = 0; c < n; ++c) {
+        int fluid = !(solid && solid[c]);
+        double u[3] = {0.0, 0.0, 0.0};
+        if (fluid) {
+            for (int q = 0; q < NQ; ++q)
+                for (int d = 0; d < 3; ++d) u[d] += C[q][d] * f[q * n + c];
+            for (int d = 0; d < 3; ++d) u[d] -= 0.5 * cfg->accel[d];
+        }
+        int on_outlet = (int)(c % cfg->nx) == cfg->nx - 1;
+        for (int q = 0; q < NQ; ++q) {
+            double s = 0.0;
+            if (fluid && kind == 0)
+                s = C[q][0] * u[0] + C[q][1] * u[1] + C[q][2] * u[2];
+            else if (fluid && kind == 1 && on_outlet)
+                s = C[q][0];
+            if (lam_seed) lam_seed[q * n + c] = s;
+        }
+        if (!fluid) continue;
+        if (kind == 0) {
+            J += 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            for (int d = 0; d < 3; ++d) da[d] += -0.5 * u[d];
+        } else if (on_outlet) {
+            J += u[0];
+            da[0] += -0.5;
+        }
+    }
+    if (dJda)
+        for (int d = 0; d < 3; ++d) dJda[d] = da[d];
+    return J;
+}
+
+/* Gradient with respect to u_init of the initial state f = f^eq(rho_init,
+ * u_init): grad_u[b][x] = sum_q lam0_q(x) d f^eq_q / d u_b. */
+void oracle_init_vjp(const oracle_cfg *cfg, const uint8_t *solid, const double *u_init,
+                     const double *lam0, double *grad_u)
+{
+    int64_t n = ncells_of(cfg);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        if (solid && solid[c]) {
+            for (int b = 0; b < 3; ++b) grad_u[b * n + c] = 0.0;
+            continue;
+        }
+        double u[3] = {u_init[c], u_init[n + c], u_init[2 * n + c]};
+        for (int b = 0; b < 3; ++b) {
+            double v = 0.0;
+            for (int q = 0; q < NQ; ++q) v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);
+            grad_u[b * n + c] = v;
+        }
+    }
+}

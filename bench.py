@@ -1,0 +1,230 @@
+"""Benchmark of the D3Q19 stream-collide + adjoint hot path on one MI355X.
+
+Workload (default): 256^3 periodic lattice, improved equilibrium (D3Q19-I),
+TRT with Lambda = 3/16, omega = 1.8, FP32 storage, two-grid pull streaming,
+seeded random-phase shear-wave initial field (8 modes, |k| <= 4, amplitudes
+U(0, 0.03)).  One timed step = one fused forward stream-collide update of
+every cell followed by one adjoint update of every cell (FP32 adjoint field,
+FP64 parameter-gradient reduction): the full differentiable lattice update.
+
+Printed: one JSON line with MLUPS (million lattice-cell updates per second,
+one update = forward + adjoint of one cell), the roofline of the dominant
+kernel from HIP events, per-kernel breakdowns, a few secondary
+configurations, and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N = 256
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip secondary configurations")
+    ap.add_argument("--n", type=int, default=N, help="cube edge (default 256)")
+    return ap.parse_args()
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _events(torch, k):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+
+
+def timed_forward(torch, lat, steps, warmup):
+    """Average duration (ms) of one fused forward step launched by lbm_step."""
+    lat.step(warmup)
+    e0, e1 = _events(torch, 2)
+    torch.cuda.synchronize()
+    e0.record()
+    lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import lbm_inputs
+    from paper_1803_04937_amd import Lattice, capi
+
+    dev = torch.device("cuda:0")
+    n = a.n
+    ncells = n ** 3
+    _log(f"inputs {n}^3 shear waves")
+    u0 = torch.tensor(lbm_inputs.shear_waves((n, n, n), seed=0), device=dev)
+    common = dict(periodic=(1, 1, 1), equilibrium="improved", collision="trt", omega=1.8,
+                  trt_magic=3.0 / 16.0, device=dev)
+
+    # ---- main timed region: forward + adjoint per step -------------------
+    lat = Lattice(n, n, n, u=u0, dtype="f32", pattern="two_grid", **common)
+    A, B = lat.buffers
+    lam = [lat.new_adjoint(), lat.new_adjoint()]
+    grad = torch.zeros(4, dtype=torch.float64, device=dev)
+    # adjoint seed: kinetic-energy objective of the initial state
+    jout = torch.zeros(4, dtype=torch.float64, device=dev)
+    lat.objective(capi.LBM_OBJ_KINETIC_ENERGY, A, jout, lam[0])
+
+    def one_step(i, ev=None):
+        src, dst = (A, B) if i % 2 == 0 else (B, A)
+        ln, lp = (lam[0], lam[1]) if i % 2 == 0 else (lam[1], lam[0])
+        if ev is not None:
+            ev[0].record()
+        lat.stream_collide(src, dst)
+        if ev is not None:
+            ev[1].record()
+        lat.adjoint_step(src, ln, lp, grad)
+        if ev is not None:
+            ev[2].record()
+
+    _log(f"warmup {a.warmup}")
+    for i in range(a.warmup):
+        one_step(i)
+    torch.cuda.synchronize()
+    evs = [_events(torch, 3) for _ in range(a.steps)]
+    _log(f"timed {a.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        one_step(a.warmup + i, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / a.steps
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / a.steps
+    step_ms = evs[0][0].elapsed_time(evs[-1][2]) / a.steps
+    if not np.isfinite(grad.cpu().numpy()).all():
+        raise RuntimeError("non-finite adjoint gradient in the timed loop")
+
+    bytes_fwd = 2 * 19 * 4 * ncells          # read + write every PDF once (FP32)
+    bytes_adj = 3 * 19 * 4 * ncells          # state + lam_next read, lam_prev written
+    fwd_gbs = bytes_fwd / (fwd_ms * 1e-3) / 1e9
+    adj_gbs = bytes_adj / (adj_ms * 1e-3) / 1e9
+    kernels = {
+        "stream_collide_f32": {"ms": fwd_ms, "bytes_per_cell": 152, "GBs": fwd_gbs,
+                               "frac": fwd_gbs / HBM_PEAK_GBS,
+                               "mlups": ncells / (fwd_ms * 1e-3) / 1e6},
+        "adjoint_f32": {"ms": adj_ms, "bytes_per_cell": 228, "GBs": adj_gbs,
+                        "frac": adj_gbs / HBM_PEAK_GBS,
+                        "mlups": ncells / (adj_ms * 1e-3) / 1e6},
+    }
+    dom = "adjoint_f32" if adj_ms >= fwd_ms else "stream_collide_f32"
+    del lam, A, B
+    lat.close()
+    del lat
+
+    # ---- secondary configurations (outside the timed region) --------------
+    extras = {}
+    if not a.no_extras:
+        for name, kw in [("fwd_f64_I_trt", dict(dtype="f64")),
+                         ("fwd_f32s_I_trt", dict(dtype="f32s")),
+                         ("fwd_f16s_I_trt", dict(dtype="f16s")),
+                         ("fwd_bf16s_I_trt", dict(dtype="bf16s")),
+                         ("fwd_f32_I_trt_aa", dict(dtype="f32", pattern="aa")),
+                         ("fwd_f16s_I_trt_aa", dict(dtype="f16s", pattern="aa"))]:
+            _log(f"extra {name}")
+            c = dict(common)
+            lat2 = Lattice(n, n, n, u=u0, **c, **kw)
+            ms = timed_forward(torch, lat2, 50, 5)
+            size = {"f64": 8, "f32": 4, "f32s": 4, "f16s": 2, "bf16s": 2}[kw["dtype"]]
+            gbs = 2 * 19 * size * ncells / (ms * 1e-3) / 1e9
+            extras[name] = {"ms": round(ms, 5), "mlups": round(ncells / (ms * 1e-3) / 1e6, 1),
+                            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            lat2.close()
+            del lat2
+            torch.cuda.empty_cache()
+        c = dict(common)
+        c.update(equilibrium="standard", collision="srt")
+        lat2 = Lattice(n, n, n, u=u0, dtype="f32", **c)
+        ms = timed_forward(torch, lat2, 50, 5)
+        extras["fwd_f32_S_srt"] = {"ms": round(ms, 5),
+                                   "mlups": round(ncells / (ms * 1e-3) / 1e6, 1)}
+        lat2.close()
+        del lat2
+        # achievable-bandwidth reference: a plain device copy of 2.55 GB
+        x = torch.empty(19 * ncells, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        e0, e1 = _events(torch, 2)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(20):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        cms = e0.elapsed_time(e1) / 20
+        extras["copy_2x2.55GB"] = {"ms": round(cms, 5),
+                                   "GBs": round(2 * x.numel() * 4 / (cms * 1e-3) / 1e9, 1)}
+        del x, y
+
+    # ---- CPU oracle baseline (bounded sample) -----------------------------
+    cpu = None
+    if not a.no_cpu:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        _log(f"cpu oracle sample on {cores} threads")
+        cfg = oracle.Config(n, n, n, improved=True, trt=True, omega=1.8, magic=3.0 / 16.0)
+        f = oracle.init(cfg, u0.cpu().numpy())
+        t0 = time.perf_counter()
+        oracle.step(cfg, f, 3)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(3 * ncells / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+               "kind": "oracle",
+               "sample": f"FP64 C oracle, forward update only, {n}^3 D3Q19-I TRT, 3 steps "
+                         f"({dt:.1f} s, {platform.processor() or platform.machine()})"}
+
+    ms_step = step_ms
+    out = {
+        "metric": "MLUPS & % HBM roofline, D3Q19 256^3 FP32/FP16 fwd + adjoint vs FP64",
+        "value": round(ncells / (ms_step * 1e-3) / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n}^3 periodic D3Q19-I TRT(Lambda=3/16) omega=1.8, FP32 "
+                               "two-grid; step = forward stream-collide + adjoint update",
+                   "cells": ncells, "init": "8 seeded shear waves |k|<=4, A~U(0,0.03)"},
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "achieved": round(kernels[dom]["GBs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(kernels[dom]["frac"], 4), "traffic": None},
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv)
+                        for kk, vv in v.items()} for k, v in kernels.items()},
+        "extras": extras,
+        "cpu_baseline": cpu,
+        "wall_s_timed": round(wall, 4),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

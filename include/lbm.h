@@ -1,0 +1,226 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D3Q19 lattice Boltzmann library.
+ *
+ * Method: Bauer & Ruede, "An improved lattice Boltzmann D3Q19 method based on
+ * an alternative equilibrium discretization" (arXiv:1803.04937).
+ *
+ * One library call = one or more HIP kernel launches on the caller's stream.
+ * All big buffers (PDF states, adjoint fields, checkpoints, moment fields)
+ * are caller-owned device memory; the library only allocates a few small
+ * scratch buffers (reduction partials) per context.  Pointers are borrowed
+ * and must outlive the context.  No function throws across the ABI: each
+ * returns an lbm_status and lbm_last_error() gives the message.  A context
+ * is not thread-safe; several contexts may coexist.  Every call is
+ * stream-ordered and asynchronous except those that return values in host
+ * memory (they synchronise the stream).
+ *
+ * Lattice (Sec. 2.3): D3Q19, directions in this fixed order, opposite
+ * directions adjacent (opposite(q) = q + 1 for odd q, q - 1 for even q > 0):
+ *    0 ( 0, 0, 0)
+ *    1 ( 1, 0, 0)   2 (-1, 0, 0)   3 ( 0, 1, 0)   4 ( 0,-1, 0)
+ *    5 ( 0, 0, 1)   6 ( 0, 0,-1)
+ *    7 ( 1, 1, 0)   8 (-1,-1, 0)   9 ( 1,-1, 0)  10 (-1, 1, 0)
+ *   11 ( 1, 0, 1)  12 (-1, 0,-1)  13 ( 1, 0,-1)  14 (-1, 0, 1)
+ *   15 ( 0, 1, 1)  16 ( 0,-1,-1)  17 ( 0, 1,-1)  18 ( 0,-1, 1)
+ * with weights 1/3 (rest), 1/18 (axis), 1/36 (edge).
+ *
+ * Cells: (x, y, z), x fastest; cell index c = (z * ny + y) * nx + x.
+ *
+ * State buffer layout (lbm_state_bytes): structure of arrays,
+ * element [q * qstride + c] of the storage type, qstride >= nx*ny*nz
+ * (padded; see lbm_qstride).  What an element holds depends on the dtype:
+ *   LBM_F64, LBM_F32            f_q (post-collision)
+ *   LBM_F32_SHIFTED             f_q - w_q
+ *   LBM_F16_SHIFTED/BF16_SHIFTED  RNE(s (f_q - w_q)), s a per-context power
+ *                               of two (lbm_scale), IEEE half / bfloat16
+ * Two-grid contexts hold f*(x) at slot [q][x].  AA contexts alternate two
+ * layouts; use lbm_get_pdfs for a canonical copy.  Adjoint fields use the
+ * same [q * qstride + c] layout with the adjoint dtype (LBM_F64 or LBM_F32).
+ *
+ * Solid cells (mask value nonzero) hold the rest state f_q = w_q, are never
+ * updated, and report rho = u = 0.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument or parameter                 */
+    LBM_ENOMEM = -2,     /* small scratch allocation failed               */
+    LBM_EHIP = -3,       /* a HIP runtime call failed                     */
+    LBM_EDIVERGED = -4,  /* watchdog: NaN/Inf or mass drift beyond bound  */
+    LBM_ESTATE = -5      /* call not valid for this context's set-up      */
+} lbm_status;
+
+/* Equilibria.  STANDARD: second-order part of eq. discreteEquilibriumStandard
+ * (Sec. 2.2) with D3Q19 weights (D3Q19-S).  IMPROVED: eq.
+ * new_d3q19_equilibrium (Sec. 3.2), built by matching 19 Maxwellian moments
+ * (D3Q19-I).  Both use rho0 = 1 unless compressible is set (Sec. 2.3). */
+enum { LBM_EQ_STANDARD = 0, LBM_EQ_IMPROVED = 1 };
+
+/* Collision.  SRT: eq. lb_srt_with_forces (Sec. 2.3).  TRT: two relaxation
+ * rates, omega (even part) and omega_minus (odd part) with
+ * Lambda = (1/omega - 1/2)(1/omega_minus - 1/2) = trt_magic; the force
+ * term, which is odd, takes the factor (1 - omega_minus/2).  The paper names
+ * TRT (Sec. 1, Sec. 3.3) without defining it. */
+enum { LBM_SRT = 0, LBM_TRT = 1 };
+
+/* Storage types of the PDF state. */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2, LBM_F16_SHIFTED = 3,
+       LBM_BF16_SHIFTED = 4 };
+
+/* Streaming patterns.  TWO_GRID: pull from one buffer into another.  AA:
+ * one buffer updated in place, alternating a step that reads and writes the
+ * cell's own slots with a step that reads and writes the neighbours'. */
+enum { LBM_TWO_GRID = 0, LBM_AA = 1 };
+
+/* Objectives of lbm_objective. */
+enum { LBM_OBJ_KINETIC_ENERGY = 0, LBM_OBJ_OUTLET_FLUX = 1 };
+
+typedef struct {
+    int32_t nx, ny, nz;       /* cells; nx*ny*nz < 2^31                           */
+    int32_t periodic[3];      /* per axis: 1 periodic, 0 half-way bounce-back walls
+                                 at both faces (Sec. 5.1)                        */
+    int32_t equilibrium;      /* LBM_EQ_*                                         */
+    int32_t collision;        /* LBM_SRT / LBM_TRT                                */
+    int32_t dtype;            /* storage, LBM_F64 ... LBM_BF16_SHIFTED             */
+    int32_t pattern;          /* LBM_TWO_GRID / LBM_AA                            */
+    int32_t compressible;     /* 0: rho0 = 1 (the paper's choice); 1: rho0 = rho   */
+    int32_t adjoint_dtype;    /* LBM_F64 (only with dtype LBM_F64) or LBM_F32      */
+    double omega;             /* SRT rate or TRT even rate, 0 < omega < 2         */
+    double trt_magic;         /* TRT Lambda > 0; ignored for SRT                  */
+    double accel[3];          /* body acceleration a; F_q = 3 w_q c_q.a (Sec. 2.3) */
+    double scale;             /* F16/BF16: s (power of two) or 0 = chosen by
+                                 lbm_init from the initial state                  */
+} lbm_params;
+
+/* Library version string. */
+const char *lbm_version(void);
+
+/* Velocity set as encoded in the library: c[19*3], w[19], opposite[19]. */
+void lbm_velocity_set(int32_t *c, double *w, int32_t *opposite);
+
+/* Padded q-stride (elements) and bytes of one PDF state buffer, and bytes of
+ * one adjoint field, for these parameters.  Host only; no GPU needed. */
+int lbm_qstride(const lbm_params *p, int64_t *qstride);
+int lbm_state_bytes(const lbm_params *p, size_t *bytes);
+int lbm_adjoint_bytes(const lbm_params *p, size_t *bytes);
+
+/* Validate p without touching the GPU.  LBM_OK or LBM_EINVAL; msg (may be
+ * NULL) receives the reason, at most msg_len bytes. */
+int lbm_validate(const lbm_params *p, char *msg, size_t msg_len);
+
+/* Create a context and write the initial state f = f^eq(rho_init, u_init)
+ * (no force shift), stored as post-collision data at t = 0.
+ *   solid    device uint8 [nz][ny][nx], nonzero = solid; NULL = all fluid
+ *   pdf0     device state buffer (lbm_state_bytes)
+ *   pdf1     second state buffer for TWO_GRID; must be NULL for AA
+ *   stream   hipStream_t (NULL = default stream)
+ *   rho_init device double [cells], or NULL for rho = 1
+ *   u_init   device double [3][cells]
+ * For F16/BF16 storage with scale == 0 the scale is
+ * s = 2^floor(log2(1024 / max |f - w|)) over the initial state.
+ * On failure *out is NULL. */
+int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid, void *pdf0, void *pdf1,
+             void *stream, const double *rho_init, const double *u_init);
+
+/* Release the context's scratch memory (not the caller's buffers). */
+void lbm_destroy(lbm_ctx *c);
+
+/* Message of the last failed call on this context (or of the last failed
+ * lbm_init when c is NULL). */
+const char *lbm_last_error(const lbm_ctx *c);
+
+/* Advance nsteps >= 0 time steps: eq. lb_srt_with_forces with pull
+ * streaming, half-way bounce-back at walls and solid cells, periodic wrap,
+ * the chosen equilibrium and collision, the force F_q and the force-shifted
+ * velocity of eq. macroscopic_vel_shift.  One fused kernel per step. */
+int lbm_step(lbm_ctx *c, int64_t nsteps);
+
+/* One two-grid step from src into dst (both state buffers of this context's
+ * layout, src != dst), leaving the context's own state untouched.  Used to
+ * recompute trajectories for the adjoint.  Two-grid contexts only. */
+int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst);
+
+/* Device pointer of the buffer that holds the current state. */
+void *lbm_current_state(lbm_ctx *c);
+
+/* Steps taken since lbm_init (AA parity is its lowest bit). */
+int64_t lbm_time(const lbm_ctx *c);
+
+/* Storage scale s of F16/BF16 contexts (1 for the others). */
+double lbm_scale(const lbm_ctx *c);
+
+/* Macroscopic moments of the current state (Sec. 2.3): rho = sum_q f*_q and
+ * u = (sum_q c_q f*_q - a/2) / rho0', which equals the equilibrium velocity
+ * of the update that produced the state.  rho: device double [cells] or
+ * NULL; u: device double [3][cells] or NULL; sums: host double[4] or NULL,
+ * receives the FP64 totals over fluid cells of rho and of sum_q c_q f*_q
+ * (mass and momentum); a non-NULL sums synchronises the stream. */
+int lbm_moments(lbm_ctx *c, double *rho, double *u, double *sums);
+
+/* Canonical copy of the current state: device double [19][cells] (dense,
+ * no padding), f*_q in FP64 whatever the dtype and AA parity. */
+int lbm_get_pdfs(lbm_ctx *c, double *canonical);
+
+/* Overwrite the current state from a canonical device double [19][cells]
+ * (quantised with the context's scale).  Solid cells are set to w_q. */
+int lbm_set_pdfs(lbm_ctx *c, const double *canonical);
+
+/* Watchdog: FP64 mass of the current state against the mass at lbm_init.
+ * LBM_EDIVERGED if a total is not finite or |mass - mass0| > rel_tol mass0.
+ * Synchronises the stream. */
+int lbm_watchdog(lbm_ctx *c, double rel_tol);
+
+/* Change omega and the body acceleration of an existing context. */
+int lbm_set_rates(lbm_ctx *c, double omega, const double *accel);
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint (not in the paper): exact transpose of one two-grid step.         */
+/* Incompressible form (compressible == 0) only.                             */
+/* ------------------------------------------------------------------------ */
+
+/* lam_prev = (d step / d f_t)^T lam_next for the step f_t -> f_{t+1}.
+ *   state_t   device state buffer (context dtype, two-grid layout) holding
+ *             f_t; the adjoint linearises at its dequantised values
+ *   lam_next  device adjoint field (adjoint dtype) at t + 1
+ *   lam_prev  device adjoint field at t (written; distinct from lam_next)
+ *   grad      device double[4] or NULL: += dJ/domega, dJ/da_x, dJ/da_y,
+ *             dJ/da_z of this step (FP64, deterministic order).  For TRT,
+ *             omega_minus follows omega at fixed Lambda.
+ * Per cell: gather as the forward step, mu = J_C^T lam_next, then write mu_r
+ * to lam_prev[r] at x - c_r, or to lam_prev[opposite(r)] at x when x - c_r
+ * is a wall or solid (every slot is written exactly once; no atomics).
+ * Solid cells copy lam_next through. */
+int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next, void *lam_prev,
+                     double *grad);
+
+/* Objective J of a stored state and its seed lam_T = dJ/df_T.
+ *   kind  LBM_OBJ_KINETIC_ENERGY: J = 1/2 sum over fluid cells of |u|^2
+ *         LBM_OBJ_OUTLET_FLUX:    J = sum of u_x over fluid cells of x = nx-1
+ *         with u the stored-state velocity of lbm_moments (rho0 = 1).
+ *   state device state buffer of this context
+ *   out   device double[4]: J and its explicit derivative dJ/da (through
+ *         u = sum c f - a/2); written (not accumulated)
+ *   lam   device adjoint field (written)                                      */
+int lbm_objective(lbm_ctx *c, int kind, const void *state, double *out, void *lam);
+
+/* Gradient with respect to u_init of f_0 = f^eq(1, u_init):
+ * grad_u[b][x] = sum_q lam0_q(x) d f^eq_q / d u_b (device double [3][cells],
+ * written; zero in solid cells).  u_init: device double [3][cells]. */
+int lbm_init_vjp(lbm_ctx *c, const double *u_init, const void *lam0, double *grad_u);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

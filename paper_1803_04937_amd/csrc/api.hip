@@ -1,0 +1,467 @@
+// C ABI of the D3Q19 stream-collide library: parameter validation, context
+// state, launch configuration and error reporting.  Kernels live in
+// forward.hip and adjoint.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "launch.h"
+#include "lbm.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+    lbm_params p;
+    Geom g;
+    bool gen;          // walls or solid cells present
+    void *buf[2];
+    int cur;           // two-grid: index of the buffer holding the state
+    hipStream_t stream;
+    int64_t t;
+    double scale;
+    double mass0;
+    CollBoth coll;
+    Scratch sc;
+    uint32_t nblocks;
+    std::string err;
+};
+
+static thread_local std::string g_init_error;
+
+static int fail(lbm_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_init_error = buf;
+    return code;
+}
+
+static int hip_fail(lbm_ctx *c, hipError_t e, const char *where) {
+    return fail(c, LBM_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+extern "C" const char *lbm_version(void) { return "lbm-d3q19-gfx950 1.0"; }
+
+extern "C" void lbm_velocity_set(int32_t *c, double *w, int32_t *o) {
+    for (int q = 0; q < Q; ++q) {
+        if (c) {
+            c[3 * q + 0] = kC[q].x;
+            c[3 * q + 1] = kC[q].y;
+            c[3 * q + 2] = kC[q].z;
+        }
+        if (w) w[q] = weight(q);
+        if (o) o[q] = opp(q);
+    }
+}
+
+static bool is_pow2(double s) {
+    if (!(s > 0.0) || !isfinite(s)) return false;
+    int e;
+    return frexp(s, &e) == 0.5;
+}
+
+static int validate(const lbm_params *p, std::string &why) {
+    if (!p) {
+        why = "params is NULL";
+        return LBM_EINVAL;
+    }
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) {
+        why = "nx, ny, nz must be >= 1";
+        return LBM_EINVAL;
+    }
+    const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    if (n >= (int64_t(1) << 31) - 4096) {
+        why = "nx*ny*nz must be below 2^31";
+        return LBM_EINVAL;
+    }
+    for (int d = 0; d < 3; ++d)
+        if (p->periodic[d] != 0 && p->periodic[d] != 1) {
+            why = "periodic[] entries must be 0 or 1";
+            return LBM_EINVAL;
+        }
+    if (p->equilibrium != LBM_EQ_STANDARD && p->equilibrium != LBM_EQ_IMPROVED) {
+        why = "unknown equilibrium";
+        return LBM_EINVAL;
+    }
+    if (p->collision != LBM_SRT && p->collision != LBM_TRT) {
+        why = "unknown collision";
+        return LBM_EINVAL;
+    }
+    if (p->dtype < LBM_F64 || p->dtype > LBM_BF16_SHIFTED) {
+        why = "unknown dtype";
+        return LBM_EINVAL;
+    }
+    if (p->pattern != LBM_TWO_GRID && p->pattern != LBM_AA) {
+        why = "unknown pattern";
+        return LBM_EINVAL;
+    }
+    if (p->compressible != 0 && p->compressible != 1) {
+        why = "compressible must be 0 or 1";
+        return LBM_EINVAL;
+    }
+    const int want_lt = p->dtype == LBM_F64 ? LBM_F64 : LBM_F32;
+    if (p->adjoint_dtype != want_lt) {
+        why = "adjoint_dtype must be LBM_F64 with dtype LBM_F64 and LBM_F32 otherwise";
+        return LBM_EINVAL;
+    }
+    if (!(p->omega > 0.0 && p->omega < 2.0)) {
+        why = "omega must lie in (0, 2)";
+        return LBM_EINVAL;
+    }
+    if (p->collision == LBM_TRT && !(p->trt_magic > 0.0 && isfinite(p->trt_magic))) {
+        why = "trt_magic must be a positive finite number";
+        return LBM_EINVAL;
+    }
+    for (int d = 0; d < 3; ++d)
+        if (!isfinite(p->accel[d])) {
+            why = "accel must be finite";
+            return LBM_EINVAL;
+        }
+    const bool q16 = p->dtype == LBM_F16_SHIFTED || p->dtype == LBM_BF16_SHIFTED;
+    if (q16 && p->scale != 0.0 && !is_pow2(p->scale)) {
+        why = "scale must be 0 or a positive power of two";
+        return LBM_EINVAL;
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_validate(const lbm_params *p, char *msg, size_t len) {
+    std::string why;
+    int rc = validate(p, why);
+    if (msg && len) {
+        snprintf(msg, len, "%s", why.c_str());
+    }
+    return rc;
+}
+
+static size_t dtype_size(int dt) {
+    switch (dt) {
+    case LBM_F64: return 8;
+    case LBM_F32:
+    case LBM_F32_SHIFTED: return 4;
+    default: return 2;
+    }
+}
+
+// Elements between consecutive q arrays: the cell count rounded up to 256
+// elements, plus an offset of 64 elements (256 B at FP32) so that the 19
+// arrays do not all start at the same large power-of-two alignment.
+static int64_t qstride_of(const lbm_params *p) {
+    const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    return ((n + 255) / 256) * 256 + 64;
+}
+
+extern "C" int lbm_qstride(const lbm_params *p, int64_t *qs) {
+    std::string why;
+    if (validate(p, why) != LBM_OK || !qs) return LBM_EINVAL;
+    *qs = qstride_of(p);
+    return LBM_OK;
+}
+
+extern "C" int lbm_state_bytes(const lbm_params *p, size_t *bytes) {
+    std::string why;
+    if (validate(p, why) != LBM_OK || !bytes) return LBM_EINVAL;
+    *bytes = (size_t)Q * qstride_of(p) * dtype_size(p->dtype);
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_bytes(const lbm_params *p, size_t *bytes) {
+    std::string why;
+    if (validate(p, why) != LBM_OK || !bytes) return LBM_EINVAL;
+    *bytes = (size_t)Q * qstride_of(p) * dtype_size(p->adjoint_dtype);
+    return LBM_OK;
+}
+
+// Relaxation and force constants of the update in both precisions.
+static void set_coll(lbm_ctx *c) {
+    const lbm_params &p = c->p;
+    const double wp = p.omega;
+    double wm = wp, kappa = 1.0;
+    if (p.collision == LBM_TRT) {
+        const double tau_p = 1.0 / wp - 0.5;
+        wm = 1.0 / (0.5 + p.trt_magic / tau_p);
+        kappa = -wm * wm * p.trt_magic / (tau_p * tau_p * wp * wp);
+    }
+    Coll<double> d;
+    d.wp = wp;
+    d.wm = wm;
+    d.kappa = kappa;
+    for (int k = 0; k < 3; ++k) d.ah[k] = 0.5 * p.accel[k];
+    for (int pp = 0; pp < 9; ++pp) {
+        const int q = 2 * pp + 1;
+        const double ca = kC[q].x * p.accel[0] + kC[q].y * p.accel[1] + kC[q].z * p.accel[2];
+        d.fraw[pp] = 3.0 * weight(q) * ca;
+        d.fpair[pp] = (1.0 - 0.5 * wm) * d.fraw[pp];
+    }
+    d.s = c->scale;
+    d.inv_s = 1.0 / c->scale;
+    d.compressible = p.compressible;
+    Coll<float> f;
+    f.wp = (float)d.wp;
+    f.wm = (float)d.wm;
+    f.kappa = (float)d.kappa;
+    for (int k = 0; k < 3; ++k) f.ah[k] = (float)d.ah[k];
+    for (int pp = 0; pp < 9; ++pp) {
+        f.fraw[pp] = (float)d.fraw[pp];
+        f.fpair[pp] = (float)d.fpair[pp];
+    }
+    f.s = (float)d.s;
+    f.inv_s = (float)d.inv_s;
+    f.compressible = d.compressible;
+    c->coll.d = d;
+    c->coll.f = f;
+}
+
+static Layout layout_of(const lbm_ctx *c) {
+    if (c->p.pattern == LBM_TWO_GRID) return kDirect;
+    return (c->t & 1) ? kAANeighbor : kAALocal;
+}
+
+static void *state_of(const lbm_ctx *c) {
+    return c->p.pattern == LBM_TWO_GRID ? c->buf[c->cur] : c->buf[0];
+}
+
+static int totals(lbm_ctx *c, double *rho, double *u, double *sums) {
+    hipError_t e = launch_moments(c->g, c->p.dtype, layout_of(c), 1.0 / c->scale,
+                                  c->p.compressible, c->coll.d.ah, state_of(c), rho, u, c->sc,
+                                  c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "moments");
+    if (sums) {
+        e = hipMemcpyAsync(sums, c->sc.result, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "moments (copy totals)");
+    }
+    return LBM_OK;
+}
+
+extern "C" void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    if (c->sc.partials) (void)hipFree(c->sc.partials);
+    if (c->sc.result) (void)hipFree(c->sc.result);
+    delete c;
+}
+
+extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid, void *pdf0,
+                        void *pdf1, void *stream, const double *rho_init, const double *u_init) {
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (validate(p, why) != LBM_OK) return fail(nullptr, LBM_EINVAL, "%s", why.c_str());
+    if (!pdf0) return fail(nullptr, LBM_EINVAL, "pdf0 is NULL");
+    if (p->pattern == LBM_TWO_GRID && (!pdf1 || pdf1 == pdf0))
+        return fail(nullptr, LBM_EINVAL, "two-grid needs a second, distinct buffer pdf1");
+    if (p->pattern == LBM_AA && pdf1)
+        return fail(nullptr, LBM_EINVAL, "the AA pattern uses one buffer; pdf1 must be NULL");
+    if (!u_init) return fail(nullptr, LBM_EINVAL, "u_init is NULL");
+
+    lbm_ctx *c = new lbm_ctx();
+    c->p = *p;
+    c->buf[0] = pdf0;
+    c->buf[1] = pdf1;
+    c->cur = 0;
+    c->stream = (hipStream_t)stream;
+    c->t = 0;
+    c->scale = 1.0;
+    Geom &g = c->g;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = p->nz;
+    g.nxy = (uint32_t)p->nx * p->ny;
+    g.ncells = g.nxy * (uint32_t)p->nz;
+    g.div_nx = make_fastdiv(g.nx);
+    g.div_ny = make_fastdiv(g.ny);
+    for (int d = 0; d < 3; ++d) g.per[d] = p->periodic[d];
+    g.qstride = qstride_of(p);
+    g.solid = solid;
+    c->gen = solid != nullptr || !(p->periodic[0] && p->periodic[1] && p->periodic[2]);
+    // host self-check of the division constants on the extreme values
+    const uint32_t probes[4] = {0u, g.nx - 1, g.nx, g.ncells - 1};
+    for (uint32_t v : probes)
+        if (fdiv(v, g.div_nx) != v / g.nx || fdiv(v, g.div_ny) != v / g.ny) {
+            delete c;
+            return fail(nullptr, LBM_EINVAL, "internal: fast division check failed");
+        }
+    c->nblocks = cell_blocks(g);
+    hipError_t e = hipMalloc(&c->sc.partials, (size_t)c->nblocks * 4 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->sc.result, 8 * sizeof(double));
+    if (e != hipSuccess) {
+        lbm_destroy(c);
+        return fail(nullptr, LBM_ENOMEM, "scratch allocation: %s", hipGetErrorString(e));
+    }
+    const bool q16 = p->dtype == LBM_F16_SHIFTED || p->dtype == LBM_BF16_SHIFTED;
+    if (q16) {
+        if (p->scale > 0.0) {
+            c->scale = p->scale;
+        } else {
+            double maxdev = 0.0;
+            e = launch_init_maxdev(g, p->equilibrium, p->compressible, rho_init, u_init, c->sc,
+                                   c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&maxdev, c->sc.result, sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) {
+                lbm_destroy(c);
+                return fail(nullptr, LBM_EHIP, "scale search: %s", hipGetErrorString(e));
+            }
+            int ex = maxdev > 0.0 ? (int)floor(log2(1024.0 / maxdev)) : 14;
+            if (ex > 40) ex = 40;
+            if (ex < -10) ex = -10;
+            c->scale = ldexp(1.0, ex);
+        }
+    }
+    set_coll(c);
+    const Layout lay = p->pattern == LBM_TWO_GRID ? kDirect : kAALocal;
+    e = launch_init(g, p->dtype, p->equilibrium, p->compressible, lay, rho_init, u_init, pdf0,
+                    p->pattern == LBM_TWO_GRID ? pdf1 : nullptr, c->scale, c->stream);
+    if (e != hipSuccess) {
+        lbm_destroy(c);
+        return fail(nullptr, LBM_EHIP, "init: %s", hipGetErrorString(e));
+    }
+    double sums[4];
+    if (totals(c, nullptr, nullptr, sums) != LBM_OK) {
+        g_init_error = c->err;
+        lbm_destroy(c);
+        return LBM_EHIP;
+    }
+    c->mass0 = sums[0];
+    *out = c;
+    return LBM_OK;
+}
+
+extern "C" const char *lbm_last_error(const lbm_ctx *c) {
+    return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
+    if (!c) return LBM_EINVAL;
+    if (n < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    for (int64_t i = 0; i < n; ++i) {
+        hipError_t e;
+        if (c->p.pattern == LBM_TWO_GRID) {
+            e = launch_step_tg(c->g, c->p.dtype, c->p.equilibrium, c->gen, c->coll,
+                               c->buf[c->cur], c->buf[1 - c->cur], c->stream);
+            if (e == hipSuccess) c->cur ^= 1;
+        } else {
+            // even step count: the state is in local layout, so the next step
+            // is a neighbour step; odd: a local step.
+            e = launch_step_aa(c->g, c->p.dtype, c->p.equilibrium, c->gen, (c->t & 1) == 0,
+                               c->coll, c->buf[0], c->stream);
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "step");
+        c->t += 1;
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst) {
+    if (!c) return LBM_EINVAL;
+    if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct buffers");
+    hipError_t e = launch_step_tg(c->g, c->p.dtype, c->p.equilibrium, c->gen, c->coll, src, dst,
+                                  c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "stream_collide");
+    return LBM_OK;
+}
+
+extern "C" void *lbm_current_state(lbm_ctx *c) { return c ? state_of(c) : nullptr; }
+
+extern "C" int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+extern "C" double lbm_scale(const lbm_ctx *c) { return c ? c->scale : 0.0; }
+
+extern "C" int lbm_moments(lbm_ctx *c, double *rho, double *u, double *sums) {
+    if (!c) return LBM_EINVAL;
+    return totals(c, rho, u, sums);
+}
+
+extern "C" int lbm_get_pdfs(lbm_ctx *c, double *canonical) {
+    if (!c) return LBM_EINVAL;
+    if (!canonical) return fail(c, LBM_EINVAL, "canonical is NULL");
+    hipError_t e = launch_get(c->g, c->p.dtype, layout_of(c), 1.0 / c->scale, state_of(c),
+                              canonical, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "get_pdfs");
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_pdfs(lbm_ctx *c, const double *canonical) {
+    if (!c) return LBM_EINVAL;
+    if (!canonical) return fail(c, LBM_EINVAL, "canonical is NULL");
+    hipError_t e = launch_set(c->g, c->p.dtype, layout_of(c), c->scale, canonical, state_of(c),
+                              c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_pdfs");
+    return LBM_OK;
+}
+
+extern "C" int lbm_watchdog(lbm_ctx *c, double rel_tol) {
+    if (!c) return LBM_EINVAL;
+    double sums[4];
+    int rc = totals(c, nullptr, nullptr, sums);
+    if (rc != LBM_OK) return rc;
+    for (int k = 0; k < 4; ++k)
+        if (!isfinite(sums[k]))
+            return fail(c, LBM_EDIVERGED, "non-finite total (mass %g, momentum %g %g %g)", sums[0],
+                        sums[1], sums[2], sums[3]);
+    if (fabs(sums[0] - c->mass0) > rel_tol * fabs(c->mass0))
+        return fail(c, LBM_EDIVERGED, "mass drift %.3e relative (mass %.17g, initial %.17g)",
+                    (sums[0] - c->mass0) / c->mass0, sums[0], c->mass0);
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_rates(lbm_ctx *c, double omega, const double *accel) {
+    if (!c) return LBM_EINVAL;
+    lbm_params p = c->p;
+    p.omega = omega;
+    if (accel)
+        for (int d = 0; d < 3; ++d) p.accel[d] = accel[d];
+    std::string why;
+    if (validate(&p, why) != LBM_OK) return fail(c, LBM_EINVAL, "%s", why.c_str());
+    c->p = p;
+    set_coll(c);
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next,
+                                void *lam_prev, double *grad) {
+    if (!c) return LBM_EINVAL;
+    if (c->p.compressible)
+        return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
+    if (!state_t || !lam_next || !lam_prev || lam_next == lam_prev)
+        return fail(c, LBM_EINVAL, "state_t, lam_next, lam_prev must be set, lam_next != lam_prev");
+    hipError_t e = launch_adjoint(c->g, c->p.dtype, c->p.adjoint_dtype, c->p.equilibrium, c->gen,
+                                  c->coll, state_t, lam_next, lam_prev, grad, c->sc, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
+    return LBM_OK;
+}
+
+extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *out, void *lam) {
+    if (!c) return LBM_EINVAL;
+    if (c->p.compressible)
+        return fail(c, LBM_ESTATE, "objectives are defined for the incompressible form only");
+    if (kind != LBM_OBJ_KINETIC_ENERGY && kind != LBM_OBJ_OUTLET_FLUX)
+        return fail(c, LBM_EINVAL, "unknown objective kind %d", kind);
+    if (!state || !out || !lam) return fail(c, LBM_EINVAL, "state, out and lam must be set");
+    hipError_t e = launch_objective(c->g, c->p.dtype, c->p.adjoint_dtype, kind, 1.0 / c->scale,
+                                    c->coll.d.ah, state, out, lam, c->sc, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "objective");
+    return LBM_OK;
+}
+
+extern "C" int lbm_init_vjp(lbm_ctx *c, const double *u_init, const void *lam0, double *grad_u) {
+    if (!c) return LBM_EINVAL;
+    if (c->p.compressible)
+        return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
+    if (!u_init || !lam0 || !grad_u) return fail(c, LBM_EINVAL, "u_init, lam0, grad_u must be set");
+    hipError_t e = launch_init_vjp(c->g, c->p.adjoint_dtype, c->p.equilibrium, u_init, lam0,
+                                   grad_u, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "init_vjp");
+    return LBM_OK;
+}

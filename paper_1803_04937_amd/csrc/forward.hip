@@ -1,0 +1,438 @@
+// Forward kernels: initial state, fused stream-collide (two-grid pull and AA
+// in-place), canonical read-out / write-in, moments and reductions.
+//
+// Update: eq. lb_srt_with_forces (Sec. 2.3) with the Buick forcing term
+// F_q = 3 w_q c_q.a, the force-shifted velocity of eq. macroscopic_vel_shift,
+// the standard (Sec. 2.2) or improved (Sec. 3.2, eq. new_d3q19_equilibrium)
+// equilibrium, half-way bounce-back and periodic wrap (Sec. 5.1).
+#include "launch.h"
+#include "reduce.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Helpers
+// ---------------------------------------------------------------------------
+
+// Shifted equilibrium f^eq_q - w_q = w_q [drho + rho0 (E + 3 c_q.u)] of all
+// 19 directions, in FP64.
+template <int EQ>
+__device__ __forceinline__ void shifted_feq(double drho, double rho0, double ux, double uy,
+                                            double uz, double (&d)[Q]) {
+    double cu[9], E[9], E0;
+    Poly::even<double, EQ>(ux, uy, uz, cu, E, E0);
+    d[0] = weight(0) * (drho + rho0 * E0);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int q = 2 * p + 1;
+        const double w = weight(q);
+        d[q] = w * (drho + rho0 * (E[p] + 3.0 * cu[p]));
+        d[q + 1] = w * (drho + rho0 * (E[p] - 3.0 * cu[p]));
+    }
+}
+
+// Slot of f*_q(x) in a buffer of the given layout.  For kAANeighbor the slot
+// lies at x + c_q unless that cell is a wall or solid.
+template <bool GEN>
+__device__ __forceinline__ void canonical_slot(const Hood &h, const Geom &g, Layout layout,
+                                               int q, int &arr, uint32_t &cell) {
+    if (layout == kDirect) {
+        arr = q;
+        cell = h.idx;
+    } else if (layout == kAALocal) {
+        arr = opp(q);
+        cell = h.idx;
+    } else {
+        bool fl;
+        const uint32_t c = hood_cell<GEN>(h, g, q, +1, fl);
+        arr = fl ? q : opp(q);
+        cell = fl ? c : h.idx;
+    }
+}
+
+__device__ __forceinline__ uint32_t cell_index() { return blockIdx.x * kBlock + threadIdx.x; }
+
+__device__ __forceinline__ bool is_solid(const Geom &g, uint32_t idx) {
+    return g.solid != nullptr && g.solid[idx] != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Initial state f = f^eq(rho, u) (no force shift); solid cells f = w.
+// Written into A (in the given layout) and, if B != null, into B as well.
+// ---------------------------------------------------------------------------
+template <int DT, int EQ>
+__global__ __launch_bounds__(kBlock) void k_init(Geom g, int compressible, Layout layout,
+                                                 const double *__restrict__ rho,
+                                                 const double *__restrict__ u,
+                                                 typename Store<DT>::T *A,
+                                                 typename Store<DT>::T *B, double s) {
+    using S = Store<DT>;
+    using R = typename S::R;
+    const uint32_t idx = cell_index();
+    if (idx >= g.ncells) return;
+    double d[Q];
+    if (is_solid(g, idx)) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) d[q] = 0.0;
+    } else {  // shifted equilibrium; written below as w + d (raw) or d (shifted)
+        const double r = rho ? rho[idx] : 1.0;
+        const double rho0 = compressible ? r : 1.0;
+        shifted_feq<EQ>(r - 1.0, rho0, u[idx], u[g.ncells + idx], u[2 * (size_t)g.ncells + idx],
+                        d);
+    }
+    const Hood h = make_hood(idx, g);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        int arr;
+        uint32_t cell;
+        canonical_slot<true>(h, g, layout, q, arr, cell);
+        S::store(A + arr * g.qstride, cell, (R)d[q], (R)weight(q), (R)s);
+        if (B) S::store(B + arr * g.qstride, cell, (R)d[q], (R)weight(q), (R)s);
+    }
+}
+
+// max over fluid cells and q of |f^eq_q - w_q| of the initial state.
+template <int EQ>
+__global__ __launch_bounds__(kBlock) void k_init_maxdev(Geom g, int compressible,
+                                                        const double *__restrict__ rho,
+                                                        const double *__restrict__ u,
+                                                        double *partials) {
+    const uint32_t idx = cell_index();
+    double m[1] = {0.0};
+    if (idx < g.ncells && !is_solid(g, idx)) {
+        const double r = rho ? rho[idx] : 1.0;
+        double d[Q];
+        shifted_feq<EQ>(r - 1.0, compressible ? r : 1.0, u[idx], u[g.ncells + idx],
+                        u[2 * (size_t)g.ncells + idx], d);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) m[0] = fmax(m[0], fabs(d[q]));
+    }
+    block_reduce<1, true>(m, partials + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Two-grid pull step: dst[q][x] = f*_q(x) from src.
+// ---------------------------------------------------------------------------
+template <int DT, int EQ, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<DT>::R> P,
+                                                    const typename Store<DT>::T *__restrict__ src,
+                                                    typename Store<DT>::T *__restrict__ dst) {
+    using S = Store<DT>;
+    using R = typename S::R;
+    const uint32_t idx = cell_index();
+    if (idx >= g.ncells) return;
+    if (GEN && is_solid(g, idx)) return;
+    const Hood h = make_hood(idx, g);
+    R d[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        bool fl;
+        const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
+        const typename S::T *p = src + (fl ? q : opp(q)) * g.qstride;
+        d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s);
+    }
+    collide<R, EQ>(d, P);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) S::store(dst + q * g.qstride, idx, d[q], (R)weight(q), P.s);
+}
+
+// ---------------------------------------------------------------------------
+// AA pattern, one buffer updated in place.
+//   neighbour step: g_q(x) = A[qbar][x - c_q] (A[q][x] if x - c_q is not
+//                   fluid); f*_q(x) -> A[q][x + c_q] (A[qbar][x] if x + c_q
+//                   is not fluid).
+//   local step:     g_q(x) = A[q][x];  f*_q(x) -> A[qbar][x].
+// Every slot a cell reads is written by the same cell, so the in-place
+// update is race-free.
+// ---------------------------------------------------------------------------
+template <int DT, int EQ, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Store<DT>::R> P,
+                                                       typename Store<DT>::T *A) {
+    using S = Store<DT>;
+    using R = typename S::R;
+    const uint32_t idx = cell_index();
+    if (idx >= g.ncells) return;
+    if (GEN && is_solid(g, idx)) return;
+    const Hood h = make_hood(idx, g);
+    R d[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        bool fl;
+        const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
+        const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
+        d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s);
+    }
+    collide<R, EQ>(d, P);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        bool fl;
+        const uint32_t c = hood_cell<GEN>(h, g, q, +1, fl);
+        typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
+        S::store(p, fl ? c : idx, d[q], (R)weight(q), P.s);
+    }
+}
+
+template <int DT, int EQ, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename Store<DT>::R> P,
+                                                        typename Store<DT>::T *A) {
+    using S = Store<DT>;
+    using R = typename S::R;
+    const uint32_t idx = cell_index();
+    if (idx >= g.ncells) return;
+    if (GEN && is_solid(g, idx)) return;
+    R d[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) d[q] = S::load(A + q * g.qstride, idx, (R)weight(q), P.inv_s);
+    collide<R, EQ>(d, P);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        S::store(A + opp(q) * g.qstride, idx, d[q], (R)weight(q), P.s);
+}
+
+// ---------------------------------------------------------------------------
+// Canonical read-out / write-in (FP64 dense [19][cells]).
+// ---------------------------------------------------------------------------
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_get(Geom g, Layout layout, double inv_s,
+                                                const typename Store<DT>::T *__restrict__ A,
+                                                double *__restrict__ out) {
+    using S = Store<DT>;
+    using R = typename S::R;
+    const uint32_t idx = cell_index();
+    if (idx >= g.ncells) return;
+    const bool solid = is_solid(g, idx);
+    const Hood h = make_hood(idx, g);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double v = weight(q);
+        if (!solid) {
+            int arr;
+            uint32_t cell;
+            canonical_slot<true>(h, g, layout, q, arr, cell);
+            v = load_canonical<DT>(A + arr * g.qstride, cell, weight(q), inv_s);
+        }
+        out[(size_t)q * g.ncells + idx] = v;
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_set(Geom g, Layout layout, double s,
+                                                const double *__restrict__ in,
+                                                typename Store<DT>::T *A) {
+    using S = Store<DT>;
+    using R = typename S::R;
+    const uint32_t idx = cell_index();
+    if (idx >= g.ncells) return;
+    const bool solid = is_solid(g, idx);
+    const Hood h = make_hood(idx, g);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (solid) {
+            S::store(A + q * g.qstride, idx, (R)0, (R)weight(q), (R)s);
+        } else {
+            int arr;
+            uint32_t cell;
+            canonical_slot<true>(h, g, layout, q, arr, cell);
+            store_canonical<DT>(A + arr * g.qstride, cell, in[(size_t)q * g.ncells + idx],
+                                weight(q), s);
+        }
+    }
+}
+
+// rho = sum f*, u = (sum c f* - a/2) / rho0' per cell (FP64), and block
+// partials of the FP64 totals of rho and sum c f* over fluid cells.
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_moments(Geom g, Layout layout, double inv_s,
+                                                    int compressible, double ahx, double ahy,
+                                                    double ahz,
+                                                    const typename Store<DT>::T *__restrict__ A,
+                                                    double *__restrict__ rho,
+                                                    double *__restrict__ u, double *partials) {
+    using S = Store<DT>;
+    using R = typename S::R;
+    const uint32_t idx = cell_index();
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    if (idx < g.ncells) {
+        double r = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
+        if (!is_solid(g, idx)) {
+            const Hood h = make_hood(idx, g);
+            double d[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                int arr;
+                uint32_t cell;
+                canonical_slot<true>(h, g, layout, q, arr, cell);
+                d[q] = (double)S::load(A + arr * g.qstride, cell, (R)weight(q), (R)inv_s);
+            }
+            double drho, jx, jy, jz;
+            moments<double>(d, drho, jx, jy, jz);
+            r = 1.0 + drho;
+            tot[0] = r;
+            tot[1] = jx;
+            tot[2] = jy;
+            tot[3] = jz;
+            const double inv = compressible ? 1.0 / r : 1.0;
+            ux = (jx - ahx) * inv;
+            uy = (jy - ahy) * inv;
+            uz = (jz - ahz) * inv;
+        }
+        if (rho) rho[idx] = r;
+        if (u) {
+            u[idx] = ux;
+            u[g.ncells + idx] = uy;
+            u[2 * (size_t)g.ncells + idx] = uz;
+        }
+    }
+    block_reduce<4>(tot, partials + 4 * (size_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Final reduction of block partials (one block, deterministic order).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials,
+                                                     uint32_t nblocks, int nvals, int op,
+                                                     double *out, int accumulate) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock)
+        for (int k = 0; k < nvals; ++k) {
+            const double x = partials[(size_t)b * nvals + k];
+            v[k] = op ? fmax(v[k], x) : v[k] + x;
+        }
+    __shared__ double res[4];
+    if (op) {
+        block_reduce<4, true>(v, res);
+    } else {
+        block_reduce<4, false>(v, res);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nvals; ++k) out[k] = accumulate ? out[k] + res[k] : res[k];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <int DT>
+static const Coll<typename Store<DT>::R> &pick(const CollBoth &P);
+template <>
+const Coll<double> &pick<LBM_F64>(const CollBoth &P) { return P.d; }
+template <>
+const Coll<float> &pick<LBM_F32>(const CollBoth &P) { return P.f; }
+template <>
+const Coll<float> &pick<LBM_F32_SHIFTED>(const CollBoth &P) { return P.f; }
+template <>
+const Coll<float> &pick<LBM_F16_SHIFTED>(const CollBoth &P) { return P.f; }
+template <>
+const Coll<float> &pick<LBM_BF16_SHIFTED>(const CollBoth &P) { return P.f; }
+
+#define LBM_DISPATCH_DT(dtype, BODY)                                  \
+    switch (dtype) {                                                  \
+    case LBM_F64: { constexpr int DT = LBM_F64; BODY; } break;                 \
+    case LBM_F32: { constexpr int DT = LBM_F32; BODY; } break;                 \
+    case LBM_F32_SHIFTED: { constexpr int DT = LBM_F32_SHIFTED; BODY; } break; \
+    case LBM_F16_SHIFTED: { constexpr int DT = LBM_F16_SHIFTED; BODY; } break; \
+    case LBM_BF16_SHIFTED: { constexpr int DT = LBM_BF16_SHIFTED; BODY; } break; \
+    default: return hipErrorInvalidValue;                             \
+    }
+
+#define LBM_DISPATCH_EQ(eq, BODY)                                        \
+    if (eq == LBM_EQ_IMPROVED) { constexpr int EQ = LBM_EQ_IMPROVED; BODY; } \
+    else { constexpr int EQ = LBM_EQ_STANDARD; BODY; }
+
+#define LBM_DISPATCH_GEN(gen, BODY)                      \
+    if (gen) { constexpr bool GEN = true; BODY; }        \
+    else { constexpr bool GEN = false; BODY; }
+
+hipError_t launch_init(const Geom &g, int dtype, int eq, int compressible, Layout layout,
+                       const double *rho, const double *u, void *A, void *B, double s,
+                       hipStream_t st) {
+    const dim3 grid(cell_blocks(g)), block(kBlock);
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, {
+        using T = typename Store<DT>::T;
+        hipLaunchKernelGGL((k_init<DT, EQ>), grid, block, 0, st, g, compressible, layout, rho, u,
+                           (T *)A, (T *)B, s);
+    }));
+    return hipGetLastError();
+}
+
+hipError_t launch_init_maxdev(const Geom &g, int eq, int compressible, const double *rho,
+                              const double *u, const Scratch &sc, hipStream_t st) {
+    const dim3 grid(cell_blocks(g)), block(kBlock);
+    LBM_DISPATCH_EQ(eq, {
+        hipLaunchKernelGGL((k_init_maxdev<EQ>), grid, block, 0, st, g, compressible, rho, u,
+                           sc.partials);
+    });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(sc.partials, cell_blocks(g), 1, 1, sc.result, false, st);
+}
+
+hipError_t launch_step_tg(const Geom &g, int dtype, int eq, bool gen, const CollBoth &P,
+                          const void *src, void *dst, hipStream_t st) {
+    const dim3 grid(cell_blocks(g)), block(kBlock);
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, {
+        using T = typename Store<DT>::T;
+        hipLaunchKernelGGL((k_step_tg<DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
+                           (const T *)src, (T *)dst);
+    })));
+    return hipGetLastError();
+}
+
+hipError_t launch_step_aa(const Geom &g, int dtype, int eq, bool gen, bool neighbor,
+                          const CollBoth &P, void *A, hipStream_t st) {
+    const dim3 grid(cell_blocks(g)), block(kBlock);
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, {
+        using T = typename Store<DT>::T;
+        if (neighbor)
+            hipLaunchKernelGGL((k_step_aa_nb<DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
+                               (T *)A);
+        else
+            hipLaunchKernelGGL((k_step_aa_loc<DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
+                               (T *)A);
+    })));
+    return hipGetLastError();
+}
+
+hipError_t launch_get(const Geom &g, int dtype, Layout layout, double inv_s, const void *A,
+                      double *out, hipStream_t st) {
+    const dim3 grid(cell_blocks(g)), block(kBlock);
+    LBM_DISPATCH_DT(dtype, {
+        using T = typename Store<DT>::T;
+        hipLaunchKernelGGL((k_get<DT>), grid, block, 0, st, g, layout, inv_s, (const T *)A, out);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_set(const Geom &g, int dtype, Layout layout, double s, const double *in,
+                      void *A, hipStream_t st) {
+    const dim3 grid(cell_blocks(g)), block(kBlock);
+    LBM_DISPATCH_DT(dtype, {
+        using T = typename Store<DT>::T;
+        hipLaunchKernelGGL((k_set<DT>), grid, block, 0, st, g, layout, s, in, (T *)A);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const Geom &g, int dtype, Layout layout, double inv_s,
+                          int compressible, const double ah[3], const void *A, double *rho,
+                          double *u, const Scratch &sc, hipStream_t st) {
+    const dim3 grid(cell_blocks(g)), block(kBlock);
+    LBM_DISPATCH_DT(dtype, {
+        using T = typename Store<DT>::T;
+        hipLaunchKernelGGL((k_moments<DT>), grid, block, 0, st, g, layout, inv_s, compressible,
+                           ah[0], ah[1], ah[2], (const T *)A, rho, u, sc.partials);
+    });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(sc.partials, cell_blocks(g), 4, 0, sc.result, false, st);
+}
+
+hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nvals, int op,
+                           double *out, bool accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, partials, nblocks, nvals, op,
+                       out, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,64 @@
+// Host-side launch interface between the C ABI (api.hip) and the kernel
+// translation units (forward.hip, adjoint.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// State layouts of a PDF buffer.
+enum Layout {
+    kDirect = 0,    // slot [q][x] holds f*_q(x)           (two-grid; AA unused)
+    kAALocal = 1,   // slot [qbar][x] holds f*_q(x)        (AA after an even step count)
+    kAANeighbor = 2 // slot [q][x + c_q] holds f*_q(x), or [qbar][x] when x + c_q
+                    // is a wall or solid                  (AA after an odd step count)
+};
+
+// Collision parameters in both compute precisions; kernels take the one of
+// their storage type.
+struct CollBoth {
+    Coll<double> d;
+    Coll<float> f;
+};
+
+// Reduction scratch: nblocks x 4 doubles of block partials.
+struct Scratch {
+    double *partials;
+    double *result;  // device double[8]
+};
+
+hipError_t launch_init(const Geom &g, int dtype, int eq, int compressible, Layout layout,
+                       const double *rho, const double *u, void *A, void *B, double s,
+                       hipStream_t st);
+hipError_t launch_init_maxdev(const Geom &g, int eq, int compressible, const double *rho,
+                              const double *u, const Scratch &sc, hipStream_t st);
+hipError_t launch_step_tg(const Geom &g, int dtype, int eq, bool gen, const CollBoth &P,
+                          const void *src, void *dst, hipStream_t st);
+hipError_t launch_step_aa(const Geom &g, int dtype, int eq, bool gen, bool neighbor,
+                          const CollBoth &P, void *A, hipStream_t st);
+hipError_t launch_get(const Geom &g, int dtype, Layout layout, double inv_s, const void *A,
+                      double *out, hipStream_t st);
+hipError_t launch_set(const Geom &g, int dtype, Layout layout, double s, const double *in,
+                      void *A, hipStream_t st);
+hipError_t launch_moments(const Geom &g, int dtype, Layout layout, double inv_s,
+                          int compressible, const double ah[3], const void *A, double *rho,
+                          double *u, const Scratch &sc, hipStream_t st);
+hipError_t launch_adjoint(const Geom &g, int dtype, int ltype, int eq, bool gen,
+                          const CollBoth &P, const void *state, const void *lam_next,
+                          void *lam_prev, double *grad, const Scratch &sc, hipStream_t st);
+hipError_t launch_objective(const Geom &g, int dtype, int ltype, int kind, double inv_s,
+                            const double ah[3], const void *state, double *out, void *lam,
+                            const Scratch &sc, hipStream_t st);
+hipError_t launch_init_vjp(const Geom &g, int ltype, int eq, const double *u, const void *lam0,
+                           double *grad_u, hipStream_t st);
+
+// Sum (op 0) or max (op 1) of nvals columns of nblocks partials into out
+// (accumulate: out += result; else out = result).  One block, fixed order.
+hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nvals, int op,
+                           double *out, bool accumulate, hipStream_t st);
+
+inline uint32_t cell_blocks(const Geom &g) { return (g.ncells + kBlock - 1) / kBlock; }
+
+}  // namespace lbm

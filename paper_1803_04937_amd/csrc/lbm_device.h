@@ -1,0 +1,392 @@
+// Device-side building blocks of the D3Q19 stream-collide library (gfx950).
+//
+// Lattice: D3Q19 (Sec. 2.3), direction order fixed by include/lbm.h.
+// Arithmetic is done in "shifted" variables d_q = f_q - w_q: moments,
+// equilibrium and collision are written in d, which keeps FP32 accurate for
+// the small deviations of f from the rest state and lets the 16-bit storage
+// formats hold s (f - w) directly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace lbm {
+
+constexpr int Q = 19;
+constexpr int kBlock = 256;  // threads per block for every cell kernel
+
+// ---------------------------------------------------------------------------
+// Velocity set (Sec. 2.3).  Opposite pairs are (2k-1, 2k), k = 1..9.
+// ---------------------------------------------------------------------------
+struct Vec3i {
+    int x, y, z;
+};
+constexpr Vec3i kC[Q] = {
+    {0, 0, 0},  {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1},
+    {-1, 0, 1}, {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+};
+__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+__host__ __device__ constexpr double weight(int q) {
+    return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---------------------------------------------------------------------------
+// Storage formats.  load() returns d = f - w in the compute type R; store()
+// takes d.  s / inv_s are the 16-bit scale and its inverse (powers of two).
+// ---------------------------------------------------------------------------
+template <int DT>
+struct Store;
+
+template <>
+struct Store<LBM_F64> {
+    using T = double;
+    using R = double;
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) { return p[i] - w; }
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) { p[i] = d + w; }
+    static __device__ __forceinline__ double load_f(const T *p, uint32_t i, double, double) {
+        return p[i];
+    }
+    static __device__ __forceinline__ void store_f(T *p, uint32_t i, double f, double, double) {
+        p[i] = f;
+    }
+};
+template <>
+struct Store<LBM_F32> {
+    using T = float;
+    using R = float;
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) { return p[i] - w; }
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) { p[i] = d + w; }
+    static __device__ __forceinline__ double load_f(const T *p, uint32_t i, double, double) {
+        return p[i];
+    }
+    static __device__ __forceinline__ void store_f(T *p, uint32_t i, double f, double, double) {
+        p[i] = (float)f;
+    }
+};
+template <>
+struct Store<LBM_F32_SHIFTED> {
+    using T = float;
+    using R = float;
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R) { return p[i]; }
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R) { p[i] = d; }
+};
+template <>
+struct Store<LBM_F16_SHIFTED> {
+    using T = _Float16;
+    using R = float;
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s) {
+        return static_cast<float>(p[i]) * inv_s;
+    }
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s) {
+        p[i] = static_cast<_Float16>(d * s);  // round to nearest even
+    }
+};
+template <>
+struct Store<LBM_BF16_SHIFTED> {
+    using T = __bf16;
+    using R = float;
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s) {
+        return static_cast<float>(p[i]) * inv_s;
+    }
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s) {
+        p[i] = static_cast<__bf16>(d * s);  // round to nearest even
+    }
+};
+
+// Canonical (FP64) access: f = w + d.  The raw formats override these with
+// exact copies.
+template <int DT>
+__device__ __forceinline__ double load_canonical(const typename Store<DT>::T *p, uint32_t i,
+                                                 double w, double inv_s) {
+    if constexpr (DT == LBM_F64 || DT == LBM_F32) {
+        return Store<DT>::load_f(p, i, w, inv_s);
+    } else {
+        using R = typename Store<DT>::R;
+        return w + (double)Store<DT>::load(p, i, (R)w, (R)inv_s);
+    }
+}
+template <int DT>
+__device__ __forceinline__ void store_canonical(typename Store<DT>::T *p, uint32_t i, double f,
+                                                double w, double s) {
+    if constexpr (DT == LBM_F64 || DT == LBM_F32) {
+        Store<DT>::store_f(p, i, f, w, s);
+    } else {
+        using R = typename Store<DT>::R;
+        Store<DT>::store(p, i, (R)(f - w), (R)w, (R)s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Unsigned 32-bit division by a run-time constant (round-up multiplier):
+// n / d = (umulhi(n, m) + n) >> l, l = ceil(log2 d), valid for all n < 2^32.
+// ---------------------------------------------------------------------------
+struct FastDiv {
+    uint32_t d, m, l;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    f.l = l;
+    f.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+    return f;
+}
+__host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+#ifdef __HIP_DEVICE_COMPILE__
+    uint32_t hi = __umulhi(n, f.m);
+#else
+    uint32_t hi = (uint32_t)(((uint64_t)n * f.m) >> 32);
+#endif
+    return (uint32_t)(((uint64_t)hi + n) >> f.l);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry shared by all cell kernels.
+// ---------------------------------------------------------------------------
+struct Geom {
+    uint32_t ncells, nx, ny, nz, nxy;
+    FastDiv div_nx, div_ny;
+    int32_t per[3];       // periodic flags
+    int64_t qstride;      // elements between consecutive q arrays
+    const uint8_t *solid; // nullptr: all fluid
+};
+
+// Per-thread neighbourhood of one cell: index offsets of x + dx, y + dy,
+// z + dz for dx, dy, dz in {-1, 0, +1} (periodic wrap applied) and whether
+// each exists (false beyond a wall).
+struct Hood {
+    uint32_t idx;
+    int32_t ox[3], oy[3], oz[3];
+    bool vx[3], vy[3], vz[3];
+};
+
+__device__ __forceinline__ Hood make_hood(uint32_t idx, const Geom &g) {
+    Hood h;
+    h.idx = idx;
+    uint32_t row = fdiv(idx, g.div_nx);
+    uint32_t x = idx - row * g.nx;
+    uint32_t z = fdiv(row, g.div_ny);
+    uint32_t y = row - z * g.ny;
+    const int32_t nx = (int32_t)g.nx, nxy = (int32_t)g.nxy, ny = (int32_t)g.ny,
+                  nz = (int32_t)g.nz;
+    h.ox[1] = 0;
+    h.oy[1] = 0;
+    h.oz[1] = 0;
+    h.vx[1] = h.vy[1] = h.vz[1] = true;
+    h.ox[0] = x == 0 ? nx - 1 : -1;
+    h.ox[2] = x == g.nx - 1 ? -(nx - 1) : 1;
+    h.vx[0] = x != 0 || g.per[0];
+    h.vx[2] = x != g.nx - 1 || g.per[0];
+    h.oy[0] = y == 0 ? (ny - 1) * nx : -nx;
+    h.oy[2] = y == g.ny - 1 ? -(ny - 1) * nx : nx;
+    h.vy[0] = y != 0 || g.per[1];
+    h.vy[2] = y != g.ny - 1 || g.per[1];
+    h.oz[0] = z == 0 ? (nz - 1) * nxy : -nxy;
+    h.oz[2] = z == g.nz - 1 ? -(nz - 1) * nxy : nxy;
+    h.vz[0] = z != 0 || g.per[2];
+    h.vz[2] = z != g.nz - 1 || g.per[2];
+    return h;
+}
+
+// Cell x + s c_q (s = -1: pull source, s = +1: push target) and whether it
+// is fluid (false for walls and solid cells).  GEN = false assumes a fully
+// periodic domain without solid cells.
+template <bool GEN>
+__device__ __forceinline__ uint32_t hood_cell(const Hood &h, const Geom &g, int q, int s,
+                                              bool &fluid) {
+    const int dx = s * kC[q].x + 1, dy = s * kC[q].y + 1, dz = s * kC[q].z + 1;
+    uint32_t c = (uint32_t)((int32_t)h.idx + h.ox[dx] + h.oy[dy] + h.oz[dz]);
+    if (!GEN) {
+        fluid = true;
+        return c;
+    }
+    bool inside = h.vx[dx] && h.vy[dy] && h.vz[dz];
+    fluid = inside && !(g.solid && g.solid[inside ? c : h.idx]);
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Collision parameters (host-prepared, compute type R).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Coll {
+    R wp, wm;       // even / odd relaxation rates (equal for SRT)
+    R ah[3];        // a / 2
+    R fpair[9];     // (1 - wm/2) * 3 w_p (c_p . a) for the pair of q = 2p + 1
+    R fraw[9];      // 3 w_p (c_p . a)
+    R kappa;        // d omega_minus / d omega (1 for SRT)
+    R s, inv_s;     // storage scale
+    int compressible;
+};
+
+// Moments of shifted PDFs: drho = sum d, j = sum c d.
+template <typename R>
+__device__ __forceinline__ void moments(const R (&d)[Q], R &drho, R &jx, R &jy, R &jz) {
+    const R p1 = d[1] - d[2], p3 = d[3] - d[4], p5 = d[5] - d[6], p7 = d[7] - d[8],
+            p9 = d[9] - d[10], p11 = d[11] - d[12], p13 = d[13] - d[14], p15 = d[15] - d[16],
+            p17 = d[17] - d[18];
+    jx = (p1 + p7) + (p9 + p11) + p13;
+    jy = (p3 + p7) - p9 + (p15 + p17);
+    jz = (p5 + p11) - p13 + (p15 - p17);
+    drho = ((d[0] + (d[1] + d[2])) + ((d[3] + d[4]) + (d[5] + d[6]))) +
+           (((d[7] + d[8]) + (d[9] + d[10])) + ((d[11] + d[12]) + (d[13] + d[14]))) +
+           ((d[15] + d[16]) + (d[17] + d[18]));
+}
+
+// Even part E_p of the equilibrium polynomial for the pair of q = 2p + 1
+// (f^eq_q - w_q = w_q [drho + rho0 (E_p + 3 c_q.u)]).  Standard:
+// E = 9/2 (c.u)^2 - 3/2 u^2.  Improved (eq. new_d3q19_equilibrium): axis
+// 6 u_a^2 - 3 u^2, edge 9/2 (c.u)^2 - 3/2 (u_a^2 + u_b^2), rest -u^2.
+struct Poly {
+    template <typename R, int EQ>
+    static __device__ __forceinline__ void even(R ux, R uy, R uz, R (&cu)[9], R (&E)[9], R &E0) {
+        const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz, uu = ux2 + uy2 + uz2;
+        cu[0] = ux;
+        cu[1] = uy;
+        cu[2] = uz;
+        cu[3] = ux + uy;
+        cu[4] = ux - uy;
+        cu[5] = ux + uz;
+        cu[6] = ux - uz;
+        cu[7] = uy + uz;
+        cu[8] = uy - uz;
+        if (EQ == LBM_EQ_IMPROVED) {
+            E0 = -uu;
+            E[0] = R(6) * ux2 - R(3) * uu;
+            E[1] = R(6) * uy2 - R(3) * uu;
+            E[2] = R(6) * uz2 - R(3) * uu;
+            const R sxy = R(1.5) * (ux2 + uy2), sxz = R(1.5) * (ux2 + uz2),
+                    syz = R(1.5) * (uy2 + uz2);
+            E[3] = R(4.5) * cu[3] * cu[3] - sxy;
+            E[4] = R(4.5) * cu[4] * cu[4] - sxy;
+            E[5] = R(4.5) * cu[5] * cu[5] - sxz;
+            E[6] = R(4.5) * cu[6] * cu[6] - sxz;
+            E[7] = R(4.5) * cu[7] * cu[7] - syz;
+            E[8] = R(4.5) * cu[8] * cu[8] - syz;
+        } else {
+            const R t = R(1.5) * uu;
+            E0 = -t;
+#pragma unroll
+            for (int p = 0; p < 9; ++p) E[p] = R(4.5) * cu[p] * cu[p] - t;
+        }
+    }
+};
+
+// Stream-collide of one cell in shifted variables, in place on d.
+template <typename R, int EQ>
+__device__ __forceinline__ void collide(R (&d)[Q], const Coll<R> &P) {
+    R drho, jx, jy, jz;
+    moments(d, drho, jx, jy, jz);
+    R rho0 = R(1), inv = R(1);
+    if (P.compressible) {
+        rho0 = R(1) + drho;
+        inv = R(1) / rho0;
+    }
+    const R ux = (jx + P.ah[0]) * inv, uy = (jy + P.ah[1]) * inv, uz = (jz + P.ah[2]) * inv;
+    R cu[9], E[9], E0;
+    Poly::even<R, EQ>(ux, uy, uz, cu, E, E0);
+    const R w0 = R(1.0 / 3.0);
+    d[0] = d[0] - P.wp * (d[0] - w0 * (drho + rho0 * E0));
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int q = 2 * p + 1;
+        const R w = R(weight(q));
+        const R np = R(0.5) * (d[q] + d[q + 1]) - w * (drho + rho0 * E[p]);
+        const R nm = R(0.5) * (d[q] - d[q + 1]) - w * rho0 * (R(3) * cu[p]);
+        const R tp = P.wp * np;
+        const R tm = P.wm * nm - P.fpair[p];
+        d[q] = d[q] - tp - tm;
+        d[q + 1] = d[q + 1] - tp + tm;
+    }
+}
+
+// Adjoint of one cell (incompressible): on entry lam = lam_{t+1}(x), d = the
+// gathered state g - w.  On exit lam = mu = J_C^T lam_{t+1}.  acc gets
+// += dJ/domega and dJ/da of this cell.
+template <typename R, int EQ, typename A>
+__device__ __forceinline__ void adjoint_cell(const R (&d)[Q], R (&lam)[Q], const Coll<R> &P,
+                                             A (&acc)[4]) {
+    R drho, jx, jy, jz;
+    moments(d, drho, jx, jy, jz);
+    const R ux = jx + P.ah[0], uy = jy + P.ah[1], uz = jz + P.ah[2];
+    R cu[9], E[9], E0;
+    Poly::even<R, EQ>(ux, uy, uz, cu, E, E0);
+    // gradient of the even parts with respect to u
+    // standard: 9 (c.u) c - 3 u; improved axis a: 12 u_a e_a - 6 u;
+    // improved edge (a, b): 9 (c.u) c - 3 (u_a e_a + u_b e_b); rest -3u / -2u.
+    R gE[9][3];
+    const R g0s = (EQ == LBM_EQ_IMPROVED) ? R(-2) : R(-3);
+    const R cxp[9] = {1, 0, 0, 1, 1, 1, 1, 0, 0};
+    const R cyp[9] = {0, 1, 0, 1, -1, 0, 0, 1, 1};
+    const R czp[9] = {0, 0, 1, 0, 0, 1, -1, 1, -1};
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        if (EQ == LBM_EQ_IMPROVED) {
+            if (p < 3) {
+                gE[p][0] = R(-6) * ux + (p == 0 ? R(12) * ux : R(0));
+                gE[p][1] = R(-6) * uy + (p == 1 ? R(12) * uy : R(0));
+                gE[p][2] = R(-6) * uz + (p == 2 ? R(12) * uz : R(0));
+            } else {
+                const R k = R(9) * cu[p];
+                gE[p][0] = k * cxp[p] - (cxp[p] != R(0) ? R(3) * ux : R(0));
+                gE[p][1] = k * cyp[p] - (cyp[p] != R(0) ? R(3) * uy : R(0));
+                gE[p][2] = k * czp[p] - (czp[p] != R(0) ? R(3) * uz : R(0));
+            }
+        } else {
+            const R k = R(9) * cu[p];
+            gE[p][0] = k * cxp[p] - R(3) * ux;
+            gE[p][1] = k * cyp[p] - R(3) * uy;
+            gE[p][2] = k * czp[p] - R(3) * uz;
+        }
+    }
+    const R w0 = R(1.0 / 3.0);
+    // rest
+    const R nu0 = P.wp * lam[0];
+    const R n0 = d[0] - w0 * (drho + E0);
+    R S0 = w0 * nu0;
+    R Vx = w0 * nu0 * g0s * ux, Vy = w0 * nu0 * g0s * uy, Vz = w0 * nu0 * g0s * uz;
+    R Ap = -lam[0] * n0, Am = R(0);
+    R Gx = 0, Gy = 0, Gz = 0;  // sum_p 2 w lam^- c_p
+    R nup[9], num[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int q = 2 * p + 1;
+        const R w = R(weight(q));
+        const R lp = R(0.5) * (lam[q] + lam[q + 1]);
+        const R lm = R(0.5) * (lam[q] - lam[q + 1]);
+        nup[p] = P.wp * lp;
+        num[p] = P.wm * lm;
+        const R np = R(0.5) * (d[q] + d[q + 1]) - w * (drho + E[p]);
+        const R nm = R(0.5) * (d[q] - d[q + 1]) - w * (R(3) * cu[p]);
+        Ap -= R(2) * lp * np;
+        Am -= R(2) * lm * (nm + R(0.5) * P.fraw[p]);
+        S0 += R(2) * w * nup[p];
+        const R t2 = R(2) * w * nup[p], t6 = R(6) * w * num[p];
+        Vx += t2 * gE[p][0] + t6 * cxp[p];
+        Vy += t2 * gE[p][1] + t6 * cyp[p];
+        Vz += t2 * gE[p][2] + t6 * czp[p];
+        const R l2w = R(2) * w * lm;
+        Gx += l2w * cxp[p];
+        Gy += l2w * cyp[p];
+        Gz += l2w * czp[p];
+    }
+    acc[0] += (A)(Ap + Am * P.kappa);
+    const R fm = R(3) * (R(1) - R(0.5) * P.wm);
+    acc[1] += (A)(R(0.5) * Vx + fm * Gx);
+    acc[2] += (A)(R(0.5) * Vy + fm * Gy);
+    acc[3] += (A)(R(0.5) * Vz + fm * Gz);
+    lam[0] = lam[0] - nu0 + S0;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int q = 2 * p + 1;
+        const R cv = cxp[p] * Vx + cyp[p] * Vy + czp[p] * Vz;
+        lam[q] = lam[q] - (nup[p] + num[p]) + S0 + cv;
+        lam[q + 1] = lam[q + 1] - (nup[p] - num[p]) + S0 - cv;
+    }
+}
+
+}  // namespace lbm

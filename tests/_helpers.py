@@ -1,0 +1,97 @@
+"""Shared helpers of the GPU parity tests: build the same case for the oracle
+and for the GPU library, move arrays between numpy and the device, and the
+tolerances used throughout.
+
+Tolerances (per PDF value, f = post-collision PDF, w_q its weight):
+  FP64 storage      |f_gpu - f_oracle| <= 1e-12 max(|f_oracle|, w_q)
+  reduced storage   one step from the same stored state:
+                    |f_gpu - f_oracle| <= half a storage ulp of the stored
+                    quantity (f, or s (f - w) for the shifted formats)
+                    + an FP32 arithmetic allowance of 2^-18 max(|f - w|, w_q / 8)
+                    (about 64 rounding errors of the largest term of the
+                    shifted update).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+
+C, W, OPP = oracle.velocity_set()
+
+DTYPE_NAMES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3, "bf16s": 4}
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def case(nx, ny, nz, periodic=(1, 1, 1), improved=True, trt=False, omega=1.2, magic=3 / 16,
+         accel=(0.0, 0.0, 0.0), solid=None, compressible=False):
+    """(oracle.Config, Lattice keyword arguments) of one case."""
+    cfg = oracle.Config(nx, ny, nz, periodic=tuple(periodic), improved=improved, trt=trt,
+                        compressible=compressible, omega=omega, magic=magic, accel=tuple(accel),
+                        solid=solid)
+    kw = dict(periodic=tuple(periodic), equilibrium="improved" if improved else "standard",
+              collision="trt" if trt else "srt", compressible=compressible, omega=omega,
+              trt_magic=magic, accel=tuple(accel))
+    if solid is not None:
+        kw["solid"] = dev(solid, torch.uint8)
+    return cfg, kw
+
+
+def lattice(cfg, kw, u, rho=None, dtype="f64", pattern="two_grid", scale=0.0):
+    from paper_1803_04937_amd import Lattice
+    return Lattice(cfg.nx, cfg.ny, cfg.nz, u=dev(u), rho=None if rho is None else dev(rho),
+                   dtype=dtype, pattern=pattern, scale=scale, **kw)
+
+
+def random_blobs(shape, seed, frac=0.08):
+    """Seeded solid mask of random boxes covering roughly frac of the cells."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    m = np.zeros(shape, np.uint8)
+    while m.mean() < frac:
+        z, y, x = rng.integers(0, nz), rng.integers(0, ny), rng.integers(0, nx)
+        dz, dy, dx = rng.integers(1, 4, size=3)
+        m[z:z + dz, y:y + dy, x:x + dx] = 1
+    return m
+
+
+def assert_f64_parity(f_gpu, f_ref, what=""):
+    bound = 1e-12 * np.maximum(np.abs(f_ref), W.reshape((19,) + (1,) * (f_ref.ndim - 1)))
+    err = np.abs(f_gpu - f_ref)
+    worst = np.max(err / bound)
+    assert worst <= 1.0, f"{what}: max error {err.max():.3e}, {worst:.2f} x bound"
+
+
+def ulp_half(x, dtype):
+    """Half a unit in the last place of |x| in the storage format."""
+    x = np.abs(x)
+    if dtype == "f16s":
+        e = np.floor(np.log2(np.maximum(x, 2.0 ** -14)))
+        return 0.5 * 2.0 ** (e - 10)
+    if dtype == "bf16s":
+        e = np.floor(np.log2(np.maximum(x, 2.0 ** -126)))
+        return 0.5 * 2.0 ** (e - 7)
+    e = np.floor(np.log2(np.maximum(x, 2.0 ** -126)))
+    return 0.5 * 2.0 ** (e - 23)
+
+
+def reduced_bound(f_ref, dtype, scale):
+    """Per-value error bound of one reduced-precision step (see module doc)."""
+    wq = W.reshape((19,) + (1,) * (f_ref.ndim - 1))
+    d = f_ref - wq
+    arith = 2.0 ** -18 * np.maximum(np.abs(d), wq / 8)
+    if dtype == "f32":
+        return ulp_half(np.abs(f_ref) + arith, "f32") + arith
+    if dtype == "f32s":
+        return ulp_half(np.abs(d) + arith, "f32") + arith
+    s = scale
+    return ulp_half(s * (np.abs(d) + arith), dtype) / s + arith

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/lbm.h, encodes the same velocity set
+as the oracle, and validates parameters before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_1803_04937_amd import capi as c
+    return c
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(capi):
+    names = _declared()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(capi.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(capi.EXPORTS) == names
+
+
+def test_velocity_set_matches_oracle(capi):
+    import oracle
+    c, w, o = capi.lbm_velocity_set()
+    oc, ow, oo = oracle.velocity_set()
+    np.testing.assert_array_equal(np.array(c), oc)
+    np.testing.assert_array_equal(np.array(w), ow)
+    np.testing.assert_array_equal(np.array(o), oo)
+
+
+def test_version(capi):
+    assert "d3q19" in capi.lbm_version()
+
+
+def test_layout_sizes(capi):
+    p = capi.make_params(256, 256, 256, dtype=capi.LBM_F32)
+    qs = capi.lbm_qstride(p)
+    assert qs >= 256 ** 3 and qs % 64 == 0
+    assert capi.lbm_state_bytes(p) == 19 * qs * 4
+    assert capi.lbm_adjoint_bytes(p) == 19 * qs * 4
+    p16 = capi.make_params(512, 512, 512, dtype=capi.LBM_F16_SHIFTED)
+    assert capi.lbm_state_bytes(p16) == 19 * capi.lbm_qstride(p16) * 2
+    p64 = capi.make_params(7, 5, 3, dtype=capi.LBM_F64)
+    assert capi.lbm_state_bytes(p64) == 19 * capi.lbm_qstride(p64) * 8
+
+
+BAD = [
+    (dict(nx=0), "nx, ny, nz"),
+    (dict(nx=2048, ny=2048, nz=512), "2^31"),
+    (dict(omega=0.0), "omega"),
+    (dict(omega=2.0), "omega"),
+    (dict(omega=float("nan")), "omega"),
+    (dict(collision=1, trt_magic=0.0), "trt_magic"),
+    (dict(collision=1, trt_magic=-1.0), "trt_magic"),
+    (dict(dtype=7), "dtype"),
+    (dict(pattern=3), "pattern"),
+    (dict(equilibrium=2), "equilibrium"),
+    (dict(collision=5), "collision"),
+    (dict(compressible=2), "compressible"),
+    (dict(periodic=(1, 2, 1)), "periodic"),
+    (dict(accel=(float("inf"), 0, 0)), "accel"),
+    (dict(dtype=0, adjoint_dtype=1), "adjoint_dtype"),
+    (dict(dtype=1, adjoint_dtype=0), "adjoint_dtype"),
+    (dict(dtype=3, scale=3.0), "power of two"),
+]
+
+
+@pytest.mark.parametrize("kw,why", BAD)
+def test_invalid_parameters_are_rejected(capi, kw, why):
+    base = dict(nx=8, ny=8, nz=8)
+    base.update(kw)
+    p = capi.make_params(**base)
+    rc, msg = capi.lbm_validate(p)
+    assert rc == capi.LBM_EINVAL
+    assert why in msg
+    # lbm_init refuses the same parameters before any GPU call
+    with pytest.raises(capi.LBMError) as e:
+        capi.lbm_init(p, None, 1 << 20, 2 << 20, None, None, 3 << 20)
+    assert e.value.status == capi.LBM_EINVAL
+    assert why in str(e.value)
+
+
+def test_init_argument_checks(capi):
+    p = capi.make_params(8, 8, 8)
+    for args, why in [((None, 0, 0, None, None, 1), "pdf0"),
+                      ((None, 16, None, None, None, 1), "second"),
+                      ((None, 16, 16, None, None, 1), "second"),
+                      ((None, 16, 32, None, None, None), "u_init")]:
+        with pytest.raises(capi.LBMError) as e:
+            capi.lbm_init(p, *args)
+        assert why in str(e.value)
+    paa = capi.make_params(8, 8, 8, pattern=capi.LBM_AA)
+    with pytest.raises(capi.LBMError) as e:
+        capi.lbm_init(paa, None, 16, 32, None, None, 1)
+    assert "one buffer" in str(e.value)
+
+
+def test_valid_parameters_pass(capi):
+    for dt in range(5):
+        p = capi.make_params(33, 17, 9, periodic=(1, 0, 0), dtype=dt, collision=capi.LBM_TRT,
+                             omega=1.95, accel=(1e-6, 0, 0))
+        assert capi.lbm_validate(p)[0] == capi.LBM_OK

@@ -39,6 +39,8 @@ def _args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip secondary configurations")
     ap.add_argument("--n", type=int, default=N, help="cube edge (default 256)")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="run one plain device copy of 19 n^3 floats (profiler reference)")
     return ap.parse_args()
 
 
@@ -133,6 +135,23 @@ def main():
                         "mlups": ncells / (adj_ms * 1e-3) / 1e6},
     }
     dom = "adjoint_f32" if adj_ms >= fwd_ms else "stream_collide_f32"
+
+    # plain copy of one state buffer with the library's copy kernel: the
+    # achievable-bandwidth reference, and the byte-count reference of the
+    # profiler's FETCH_SIZE / WRITE_SIZE runs
+    state_bytes = A.numel() * A.element_size()
+    copy_ms = None
+    if a.copy_ref or not a.no_extras:
+        lat.copy_state(A, B)
+        e0, e1 = _events(torch, 2)
+        torch.cuda.synchronize()
+        e0.record()
+        reps = 1 if a.copy_ref else 20
+        for _ in range(reps):
+            lat.copy_state(A, B)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_ms = e0.elapsed_time(e1) / reps
     del lam, A, B
     lat.close()
     del lat
@@ -165,21 +184,9 @@ def main():
                                    "mlups": round(ncells / (ms * 1e-3) / 1e6, 1)}
         lat2.close()
         del lat2
-        # achievable-bandwidth reference: a plain device copy of 2.55 GB
-        x = torch.empty(19 * ncells, dtype=torch.float32, device=dev)
-        y = torch.empty_like(x)
-        y.copy_(x)
-        e0, e1 = _events(torch, 2)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(20):
-            y.copy_(x)
-        e1.record()
-        torch.cuda.synchronize()
-        cms = e0.elapsed_time(e1) / 20
-        extras["copy_2x2.55GB"] = {"ms": round(cms, 5),
-                                   "GBs": round(2 * x.numel() * 4 / (cms * 1e-3) / 1e9, 1)}
-        del x, y
+    if copy_ms is not None:
+        extras["copy_state_f32"] = {"ms": round(copy_ms, 5), "bytes": 2 * state_bytes,
+                                    "GBs": round(2 * state_bytes / (copy_ms * 1e-3) / 1e9, 1)}
 
     # ---- CPU oracle baseline (bounded sample) -----------------------------
     cpu = None
@@ -189,12 +196,13 @@ def main():
         _log(f"cpu oracle sample on {cores} threads")
         cfg = oracle.Config(n, n, n, improved=True, trt=True, omega=1.8, magic=3.0 / 16.0)
         f = oracle.init(cfg, u0.cpu().numpy())
+        nsteps = 20
         t0 = time.perf_counter()
-        oracle.step(cfg, f, 3)
+        oracle.step(cfg, f, nsteps)
         dt = time.perf_counter() - t0
-        cpu = {"value": round(3 * ncells / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+        cpu = {"value": round(nsteps * ncells / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
                "kind": "oracle",
-               "sample": f"FP64 C oracle, forward update only, {n}^3 D3Q19-I TRT, 3 steps "
+               "sample": f"FP64 C oracle, forward update only, {n}^3 D3Q19-I TRT, {nsteps} steps "
                          f"({dt:.1f} s, {platform.processor() or platform.machine()})"}
 
     ms_step = step_ms

@@ -146,13 +146,18 @@ const char *lbm_last_error(const lbm_ctx *c);
  * velocity of eq. macroscopic_vel_shift.  One fused kernel per step. */
 int lbm_step(lbm_ctx *c, int64_t nsteps);
 
-/* One two-grid step from src into dst (both state buffers of this context's
- * layout, src != dst), leaving the context's own state untouched.  Used to
- * recompute trajectories for the adjoint.  Two-grid contexts only. */
+/* One two-grid step from src into dst (state buffers of this context's dtype
+ * in the two-grid layout, src != dst), leaving the context's own state
+ * untouched.  Used to recompute trajectories for the adjoint; allowed for
+ * contexts of either pattern. */
 int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst);
 
 /* Device pointer of the buffer that holds the current state. */
 void *lbm_current_state(lbm_ctx *c);
+
+/* Copy one state buffer (lbm_state_bytes bytes) from src to dst, e.g. to
+ * take or restore a checkpoint.  Stream-ordered. */
+int lbm_copy_state(lbm_ctx *c, const void *src, void *dst);
 
 /* Steps taken since lbm_init (AA parity is its lowest bit). */
 int64_t lbm_time(const lbm_ctx *c);

@@ -61,7 +61,8 @@ class _Rollout(torch.autograd.Function):
         ckpts = {}
         for t in range(cfg.steps):
             if t % C == 0:
-                ckpts[t] = lat.state.clone()
+                ckpts[t] = lat.new_state()
+                lat.copy_state(lat.state, ckpts[t])
             lat.step(1)
         out = torch.zeros(4, dtype=torch.float64, device=u_init.device)
         lam_T = lat.new_adjoint(zero=False)

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
 EXPORTS = [
     "lbm_version", "lbm_velocity_set", "lbm_qstride", "lbm_state_bytes", "lbm_adjoint_bytes",
     "lbm_validate", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_step",
-    "lbm_stream_collide", "lbm_current_state", "lbm_time", "lbm_scale", "lbm_moments",
+    "lbm_stream_collide", "lbm_current_state", "lbm_copy_state", "lbm_time", "lbm_scale", "lbm_moments",
     "lbm_get_pdfs", "lbm_set_pdfs", "lbm_watchdog", "lbm_set_rates", "lbm_adjoint_step",
     "lbm_objective", "lbm_init_vjp",
 ]
@@ -73,6 +73,7 @@ def _load():
         "lbm_step": ([P, ctypes.c_int64], ctypes.c_int),
         "lbm_stream_collide": ([P, P, P], ctypes.c_int),
         "lbm_current_state": ([P], P),
+        "lbm_copy_state": ([P, P, P], ctypes.c_int),
         "lbm_time": ([P], ctypes.c_int64),
         "lbm_scale": ([P], ctypes.c_double),
         "lbm_moments": ([P, P, P, P], ctypes.c_int),
@@ -202,6 +203,10 @@ def lbm_stream_collide(ctx, src, dst) -> None:
 
 def lbm_current_state(ctx) -> int:
     return _lib.lbm_current_state(ctx)
+
+
+def lbm_copy_state(ctx, src, dst) -> None:
+    _check(_lib.lbm_copy_state(ctx, _addr(src), _addr(dst)), ctx)
 
 
 def lbm_time(ctx) -> int:

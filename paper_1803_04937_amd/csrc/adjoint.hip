@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
         if (GEN && g.solid && g.solid[idx]) {
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                lam_prev[q * g.qstride + idx] = lam_next[q * g.qstride + idx];
+                st(lam_prev + q * g.qstride + idx, ld(lam_next + q * g.qstride + idx));
         } else {
             const Hood h = make_hood(idx, g);
             R d[Q], lam[Q];
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
                 const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
                 const typename S::T *p = state + (fl ? q : opp(q)) * g.qstride;
                 d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s);
-                lam[q] = (R)lam_next[q * g.qstride + idx];
+                lam[q] = (R)ld(lam_next + q * g.qstride + idx);
             }
             adjoint_cell<R, EQ>(d, lam, P, acc);
 #pragma unroll
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
                 bool fl;
                 const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
                 L *p = lam_prev + (fl ? q : opp(q)) * g.qstride;
-                p[fl ? c : idx] = (L)lam[q];
+                st(p + (fl ? c : idx), (L)lam[q]);
             }
         }
     }
@@ -205,7 +205,7 @@ hipError_t launch_adjoint(const Geom &g, int dtype, int ltype, int eq, bool gen,
 #undef LBM_ADJ
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !want) return e;
-    return launch_finalize(sc.partials, cell_blocks(g), 4, 0, grad, true, st);
+    return launch_finalize(sc, cell_blocks(g), 4, 0, grad, true, st);
 }
 
 hipError_t launch_objective(const Geom &g, int dtype, int ltype, int kind, double inv_s,
@@ -232,7 +232,7 @@ hipError_t launch_objective(const Geom &g, int dtype, int ltype, int kind, doubl
 #undef LBM_OBJ
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_finalize(sc.partials, cell_blocks(g), 4, 0, out, false, st);
+    return launch_finalize(sc, cell_blocks(g), 4, 0, out, false, st);
 }
 
 hipError_t launch_init_vjp(const Geom &g, int ltype, int eq, const double *u, const void *lam0,

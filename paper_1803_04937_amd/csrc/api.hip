@@ -246,6 +246,7 @@ static int totals(lbm_ctx *c, double *rho, double *u, double *sums) {
 extern "C" void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     if (c->sc.partials) (void)hipFree(c->sc.partials);
+    if (c->sc.stage) (void)hipFree(c->sc.stage);
     if (c->sc.result) (void)hipFree(c->sc.result);
     delete c;
 }
@@ -291,7 +292,9 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
             return fail(nullptr, LBM_EINVAL, "internal: fast division check failed");
         }
     c->nblocks = cell_blocks(g);
+    c->sc.stage_half = (size_t)((c->nblocks + kReduceChunk - 1) / kReduceChunk) * 4;
     hipError_t e = hipMalloc(&c->sc.partials, (size_t)c->nblocks * 4 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->sc.stage, 2 * c->sc.stage_half * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->sc.result, 8 * sizeof(double));
     if (e != hipSuccess) {
         lbm_destroy(c);
@@ -373,6 +376,16 @@ extern "C" int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst) {
 }
 
 extern "C" void *lbm_current_state(lbm_ctx *c) { return c ? state_of(c) : nullptr; }
+
+extern "C" int lbm_copy_state(lbm_ctx *c, const void *src, void *dst) {
+    if (!c) return LBM_EINVAL;
+    if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct buffers");
+    size_t bytes = 0;
+    lbm_state_bytes(&c->p, &bytes);
+    hipError_t e = launch_copy(src, dst, bytes, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "copy_state");
+    return LBM_OK;
+}
 
 extern "C" int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
 

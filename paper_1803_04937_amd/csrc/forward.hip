@@ -287,26 +287,63 @@ __global__ __launch_bounds__(kBlock) void k_moments(Geom g, Layout layout, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Final reduction of block partials (one block, deterministic order).
+// Final reduction of block partials (deterministic: fixed fold order).
 // ---------------------------------------------------------------------------
+template <bool MAX>
+__device__ __forceinline__ void fold_chunk(const double *__restrict__ in, uint32_t first,
+                                           uint32_t count, int nvals, double (&v)[4]) {
+    for (uint32_t i = threadIdx.x; i < count; i += kBlock)
+        for (int k = 0; k < nvals; ++k) {
+            const double x = in[(size_t)(first + i) * nvals + k];
+            v[k] = MAX ? fmax(v[k], x) : v[k] + x;
+        }
+}
+
+// One pass: block b folds entries [b * kReduceChunk, (b + 1) * kReduceChunk).
+__global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *__restrict__ in,
+                                                         uint32_t n, int nvals, int op,
+                                                         double *__restrict__ out) {
+    const uint32_t first = blockIdx.x * kReduceChunk;
+    const uint32_t count = min(kReduceChunk, n - first);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    __shared__ double res[4];
+    if (op) {
+        fold_chunk<true>(in, first, count, nvals, v);
+        block_reduce<4, true>(v, res);
+    } else {
+        fold_chunk<false>(in, first, count, nvals, v);
+        block_reduce<4, false>(v, res);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nvals; ++k) out[(size_t)blockIdx.x * nvals + k] = res[k];
+}
+
+// Last pass (n <= kReduceChunk): one block writes or accumulates out.
 __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials,
                                                      uint32_t nblocks, int nvals, int op,
                                                      double *out, int accumulate) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock)
-        for (int k = 0; k < nvals; ++k) {
-            const double x = partials[(size_t)b * nvals + k];
-            v[k] = op ? fmax(v[k], x) : v[k] + x;
-        }
     __shared__ double res[4];
     if (op) {
+        fold_chunk<true>(partials, 0, nblocks, nvals, v);
         block_reduce<4, true>(v, res);
     } else {
+        fold_chunk<false>(partials, 0, nblocks, nvals, v);
         block_reduce<4, false>(v, res);
     }
     __syncthreads();
     if (threadIdx.x == 0)
         for (int k = 0; k < nvals; ++k) out[k] = accumulate ? out[k] + res[k] : res[k];
+}
+
+// Plain 16-byte-wide copy (checkpoints, and the byte-count reference of the
+// profiler runs).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kBlock) void k_copy(const u32x4 *__restrict__ src,
+                                                 u32x4 *__restrict__ dst, size_t n16) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // ---------------------------------------------------------------------------
@@ -365,7 +402,7 @@ hipError_t launch_init_maxdev(const Geom &g, int eq, int compressible, const dou
     });
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_finalize(sc.partials, cell_blocks(g), 1, 1, sc.result, false, st);
+    return launch_finalize(sc, cell_blocks(g), 1, 1, sc.result, false, st);
 }
 
 hipError_t launch_step_tg(const Geom &g, int dtype, int eq, bool gen, const CollBoth &P,
@@ -425,13 +462,35 @@ hipError_t launch_moments(const Geom &g, int dtype, Layout layout, double inv_s,
     });
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_finalize(sc.partials, cell_blocks(g), 4, 0, sc.result, false, st);
+    return launch_finalize(sc, cell_blocks(g), 4, 0, sc.result, false, st);
 }
 
-hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nvals, int op,
-                           double *out, bool accumulate, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, partials, nblocks, nvals, op,
-                       out, accumulate ? 1 : 0);
+hipError_t launch_finalize(const Scratch &sc, uint32_t nblocks, int nvals, int op, double *out,
+                           bool accumulate, hipStream_t st) {
+    const double *src = sc.partials;
+    uint32_t n = nblocks;
+    int half = 0;
+    while (n > kReduceChunk) {
+        const uint32_t m = (n + kReduceChunk - 1) / kReduceChunk;
+        double *dst = sc.stage + half * sc.stage_half;
+        hipLaunchKernelGGL(k_reduce_stage, dim3(m), dim3(kBlock), 0, st, src, n, nvals, op, dst);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        src = dst;
+        n = m;
+        half ^= 1;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, src, n, nvals, op, out,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t st) {
+    if (nbytes % 16) return hipErrorInvalidValue;
+    const size_t n16 = nbytes / 16;
+    const size_t blocks = (n16 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(kBlock), 0, st, (const u32x4 *)src,
+                       (u32x4 *)dst, n16);
     return hipGetLastError();
 }
 

@@ -23,11 +23,16 @@ struct CollBoth {
     Coll<float> f;
 };
 
-// Reduction scratch: nblocks x 4 doubles of block partials.
+// Reduction scratch: nblocks x 4 doubles of block partials, a two-half
+// staging area for the multi-pass final reduction, and a small result slot.
 struct Scratch {
     double *partials;
-    double *result;  // device double[8]
+    double *stage;        // 2 x stage_half doubles
+    size_t stage_half;    // ceil(nblocks / kReduceChunk) * 4
+    double *result;       // device double[8]
 };
+
+constexpr uint32_t kReduceChunk = 1024;  // partials folded per block and pass
 
 hipError_t launch_init(const Geom &g, int dtype, int eq, int compressible, Layout layout,
                        const double *rho, const double *u, void *A, void *B, double s,
@@ -55,9 +60,13 @@ hipError_t launch_init_vjp(const Geom &g, int ltype, int eq, const double *u, co
                            double *grad_u, hipStream_t st);
 
 // Sum (op 0) or max (op 1) of nvals columns of nblocks partials into out
-// (accumulate: out += result; else out = result).  One block, fixed order.
-hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nvals, int op,
-                           double *out, bool accumulate, hipStream_t st);
+// (accumulate: out += result; else out = result).  Passes of 1024-way folds,
+// then one block; the order of every addition is fixed.
+hipError_t launch_finalize(const Scratch &sc, uint32_t nblocks, int nvals, int op, double *out,
+                           bool accumulate, hipStream_t st);
+
+// Plain copy of nbytes (a multiple of 16) from src to dst.
+hipError_t launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t st);
 
 inline uint32_t cell_blocks(const Geom &g) { return (g.ncells + kBlock - 1) / kBlock; }
 

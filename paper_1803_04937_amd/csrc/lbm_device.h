@@ -34,6 +34,31 @@ __host__ __device__ constexpr double weight(int q) {
 }
 
 // ---------------------------------------------------------------------------
+// Streaming memory access.  Every PDF and adjoint value is read once and
+// written once per step, so loads and stores carry the non-temporal hint.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+__device__ __forceinline__ _Float16 ld(const _Float16 *p) {
+    return __builtin_bit_cast(_Float16, __builtin_nontemporal_load((const uint16_t *)p));
+}
+__device__ __forceinline__ void st(_Float16 *p, _Float16 v) {
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t *)p);
+}
+__device__ __forceinline__ __bf16 ld(const __bf16 *p) {
+    return __builtin_bit_cast(__bf16, __builtin_nontemporal_load((const uint16_t *)p));
+}
+__device__ __forceinline__ void st(__bf16 *p, __bf16 v) {
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t *)p);
+}
+
+// ---------------------------------------------------------------------------
 // Storage formats.  load() returns d = f - w in the compute type R; store()
 // takes d.  s / inv_s are the 16-bit scale and its inverse (powers of two).
 // ---------------------------------------------------------------------------
@@ -44,44 +69,44 @@ template <>
 struct Store<LBM_F64> {
     using T = double;
     using R = double;
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) { return p[i] - w; }
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) { p[i] = d + w; }
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) { return ld(p + i) - w; }
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) { st(p + i, (T)(d + w)); }
     static __device__ __forceinline__ double load_f(const T *p, uint32_t i, double, double) {
-        return p[i];
+        return ld(p + i);
     }
     static __device__ __forceinline__ void store_f(T *p, uint32_t i, double f, double, double) {
-        p[i] = f;
+        st(p + i, f);
     }
 };
 template <>
 struct Store<LBM_F32> {
     using T = float;
     using R = float;
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) { return p[i] - w; }
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) { p[i] = d + w; }
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) { return ld(p + i) - w; }
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) { st(p + i, (T)(d + w)); }
     static __device__ __forceinline__ double load_f(const T *p, uint32_t i, double, double) {
-        return p[i];
+        return ld(p + i);
     }
     static __device__ __forceinline__ void store_f(T *p, uint32_t i, double f, double, double) {
-        p[i] = (float)f;
+        st(p + i, (float)f);
     }
 };
 template <>
 struct Store<LBM_F32_SHIFTED> {
     using T = float;
     using R = float;
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R) { return p[i]; }
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R) { p[i] = d; }
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R) { return ld(p + i); }
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R) { st(p + i, d); }
 };
 template <>
 struct Store<LBM_F16_SHIFTED> {
     using T = _Float16;
     using R = float;
     static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s) {
-        return static_cast<float>(p[i]) * inv_s;
+        return static_cast<float>(ld(p + i)) * inv_s;
     }
     static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s) {
-        p[i] = static_cast<_Float16>(d * s);  // round to nearest even
+        st(p + i, static_cast<_Float16>(d * s));  // round to nearest even
     }
 };
 template <>
@@ -89,10 +114,10 @@ struct Store<LBM_BF16_SHIFTED> {
     using T = __bf16;
     using R = float;
     static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s) {
-        return static_cast<float>(p[i]) * inv_s;
+        return static_cast<float>(ld(p + i)) * inv_s;
     }
     static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s) {
-        p[i] = static_cast<__bf16>(d * s);  // round to nearest even
+        st(p + i, static_cast<__bf16>(d * s));  // round to nearest even
     }
 };
 

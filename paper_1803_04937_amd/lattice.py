@@ -118,6 +118,9 @@ class Lattice:
     def stream_collide(self, src: torch.Tensor, dst: torch.Tensor) -> None:
         capi.lbm_stream_collide(self.ctx, src, dst)
 
+    def copy_state(self, src: torch.Tensor, dst: torch.Tensor) -> None:
+        capi.lbm_copy_state(self.ctx, src, dst)
+
     def moments(self):
         """(rho (nz,ny,nx), u (3,nz,ny,nx)) FP64 device tensors."""
         rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)

@@ -230,3 +230,16 @@ def test_mass_conservation_fp64_long_run():
     m0 = lat.totals()[0]
     lat.step(1000)
     assert abs(lat.totals()[0] - m0) / m0 < 1e-13
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f16s"])
+def test_copy_state_is_exact(dtype):
+    """lbm_copy_state copies a whole state buffer bit for bit (checkpoints)."""
+    cfg, kw = case(21, 13, 9, trt=True, omega=1.3)
+    lat = lattice(cfg, kw, lbm_inputs.shear_waves(cfg.shape, seed=20), dtype=dtype)
+    lat.step(3)
+    dst = lat.new_state()
+    lat.copy_state(lat.state, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(dst.view(torch.uint8 if dtype == "f64" else torch.int16),
+                       lat.state.view(torch.uint8 if dtype == "f64" else torch.int16))

@@ -1,0 +1,82 @@
+"""Parity at full workload sizes, in the launch configurations the benchmark
+times: one GPU step from a stored state against the FP64 oracle evaluated
+cell by cell on a seeded sample (plus every corner and edge cell)."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from _helpers import case, host, lattice, reduced_bound
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample(shape, seed, k=4096):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    cells = set(rng.choice(nx * ny * nz, size=k, replace=False).tolist())
+    for z in (0, nz - 1):
+        for y in (0, ny - 1):
+            for x in (0, 1, nx - 2, nx - 1):
+                cells.add((z * ny + y) * nx + x)
+    return np.array(sorted(cells), dtype=np.int64)
+
+
+def _sampled_step(cfg, kw, u0, dtype, pattern, warm, seed):
+    lat = lattice(cfg, kw, u0, dtype=dtype, pattern=pattern)
+    lat.step(warm)
+    f_in = host(lat.get_pdfs())
+    lat.step(1)
+    cells = _sample(cfg.shape, seed)
+    got = lat.get_pdfs().view(19, -1)[:, torch.as_tensor(cells, device="cuda")]
+    got = host(got)
+    want = oracle.step_cells(cfg, f_in, cells).T
+    del f_in
+    return got, want, lat.scale
+
+
+@pytest.mark.parametrize("pattern,warm", [("two_grid", 5), ("aa", 5), ("aa", 6)])
+def test_bench_workload_256_f32(pattern, warm):
+    """256^3 periodic D3Q19-I TRT, omega = 1.8, FP32 (the timed workload)."""
+    n = 256
+    cfg, kw = case(n, n, n, improved=True, trt=True, omega=1.8)
+    u0 = lbm_inputs.shear_waves((n, n, n), seed=0)
+    got, want, s = _sampled_step(cfg, kw, u0, "f32", pattern, warm, seed=1)
+    assert np.all(np.abs(got - want) <= reduced_bound(want, "f32", s))
+
+
+@pytest.mark.parametrize("dtype", ["f16s", "bf16s", "f32s"])
+def test_512_reduced_precision(dtype):
+    """512^3 periodic D3Q19-I TRT, omega = 1.98, 16-bit shifted storage."""
+    n = 512
+    cfg, kw = case(n, n, n, improved=True, trt=True, omega=1.98)
+    u0 = lbm_inputs.shear_waves((n, n, n), seed=2, amax=0.04)
+    got, want, s = _sampled_step(cfg, kw, u0, dtype, "two_grid", 3, seed=3)
+    assert np.all(np.abs(got - want) <= reduced_bound(want, dtype, s))
+
+
+def test_256_fp64_standard_srt():
+    """256^3 FP64 D3Q19-S SRT, omega = 1.0: the oracle-matched precision."""
+    n = 256
+    cfg, kw = case(n, n, n, improved=False, trt=False, omega=1.0)
+    u0 = lbm_inputs.shear_waves((n, n, n), seed=4)
+    got, want, _ = _sampled_step(cfg, kw, u0, "f64", "two_grid", 4, seed=5)
+    W = oracle.velocity_set()[1][:, None]
+    assert np.all(np.abs(got - want) <= 1e-12 * np.maximum(np.abs(want), W))
+
+
+def test_tube_192x192x768_f16_walls():
+    """The constricted-tube geometry at full size (solid mask, TRT, body
+    force), FP16 storage: sampled one-step parity including cells next to the
+    wall."""
+    nx, ny, nz = 768, 192, 192
+    solid = lbm_inputs.tube_mask(nx, ny, nz)
+    cfg, kw = case(nx, ny, nz, periodic=(1, 1, 1), improved=True, trt=True, omega=1.95,
+                   accel=(2e-6, 0, 0), solid=solid)
+    rng = np.random.default_rng(6)
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = 0.02 * (solid == 0)
+    u0 += rng.uniform(-1e-3, 1e-3, size=u0.shape) * (solid == 0)
+    got, want, s = _sampled_step(cfg, kw, u0, "f16s", "two_grid", 4, seed=7)
+    assert np.all(np.abs(got - want) <= reduced_bound(want, "f16s", s))

@@ -1,0 +1,146 @@
+"""Full workloads: the reduced-precision error table against the FP64 oracle,
+and gradients of the full-size adjoint configurations against finite
+differences of FP64 runs.  Each test prints the figures it measures."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from _helpers import case, dev, host, lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def _errors(u, rho, u_ref, rho_ref):
+    """Velocity: ||u - u_ref||_2 / ||u_ref||_2; density: RMS(rho - rho_ref) and
+    that divided by RMS(rho_ref - 1)."""
+    eu = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+    er = np.sqrt(np.mean((rho - rho_ref) ** 2))
+    return eu, er, er / np.sqrt(np.mean((rho_ref - 1.0) ** 2))
+
+
+def test_spectrum_64_precision_table():
+    """64^3 periodic, k^4 exp(-2 (k/8)^2) spectrum, max |u| = 0.08, D3Q19-I TRT,
+    omega = 1.98, 2000 steps: error of every storage format against the FP64
+    oracle."""
+    n, T = 64, 2000
+    cfg, kw = case(n, n, n, improved=True, trt=True, omega=1.98)
+    u0 = lbm_inputs.spectrum_field(n, seed=8)
+    f_ref = oracle.step(cfg, oracle.init(cfg, u0), T)
+    rho_ref, u_ref = oracle.moments(cfg, f_ref)
+    table = {}
+    for dtype in ("f64", "f32", "f32s", "f16s", "bf16s"):
+        lat = lattice(cfg, kw, u0, dtype=dtype)
+        lat.step(T)
+        rho, u = lat.moments()
+        eu, er, er_rel = _errors(host(u), host(rho), u_ref, rho_ref)
+        table[dtype] = {"u_rel_l2": eu, "rho_rms": er, "rho_rms_rel": er_rel}
+        lat.close()
+    print("\nprecision table 64^3 T=2000:", json.dumps(table))
+    # measured on MI355X: 1.4e-13, 9.9e-6, 1.9e-6, 1.9e-3, 1.7e-2
+    assert table["f64"]["u_rel_l2"] < 1e-11
+    assert table["f32s"]["u_rel_l2"] < table["f32"]["u_rel_l2"]
+    assert table["f32"]["u_rel_l2"] < 5e-5
+    assert table["f16s"]["u_rel_l2"] < 1e-2
+    assert table["bf16s"]["u_rel_l2"] < 1e-1
+
+
+def _fd_rollout(nx, ny, nz, T, u0, accel, omega, kind, periodic, collision, solid=None):
+    """J(f_T) of an FP64 forward run (the oracle-matched precision)."""
+    from paper_1803_04937_amd import Lattice
+    lat = Lattice(nx, ny, nz, u=dev(u0), solid=solid, periodic=periodic,
+                  equilibrium="improved", collision=collision, dtype="f64", omega=omega,
+                  accel=tuple(accel))
+    lat.step(T)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    lam = lat.new_adjoint(zero=False)
+    lat.objective(kind, lat.state, out, lam)
+    J = out[0].item()
+    lat.close()
+    del lam, lat
+    return J
+
+
+def test_duct_128x128x512_srt_gradient_fp32():
+    """Duct 512 x 128 x 128 (x periodic, half-way walls on y and z), D3Q19-I SRT,
+    omega = 1.9, g_x = 1e-6, FP32 forward and adjoint, T = 500 with a
+    checkpoint every 50 steps.  Kinetic-energy gradient with respect to g_x,
+    omega and the initial velocity (seeded direction) against central
+    differences (relative step 1e-4) of FP64 runs."""
+    from paper_1803_04937_amd import RolloutConfig, rollout_objective
+    nx, ny, nz, T = 512, 128, 128, 500
+    gx, omega = 1e-6, 1.9
+    nu = (1 / omega - 0.5) / 3
+    u0 = lbm_inputs.duct_poiseuille(nx, ny, nz, gx, nu) + lbm_inputs.perturbation(
+        (nz, ny, nx), seed=9, amp=1e-3)
+    rc = RolloutConfig(nx, ny, nz, steps=T, periodic=(1, 0, 0), collision="srt", dtype="f32",
+                       objective=0, checkpoint_every=50)
+    u = dev(u0).requires_grad_(True)
+    a = torch.tensor([gx, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    w = torch.tensor(omega, dtype=torch.float64, requires_grad=True)
+    J32 = rollout_objective(u, a, w, rc)
+    J32.backward()
+    h = 1e-4
+    args = dict(kind=0, periodic=(1, 0, 0), collision="srt")
+    J64 = _fd_rollout(nx, ny, nz, T, u0, [gx, 0, 0], omega, **args)
+    fd_a = (_fd_rollout(nx, ny, nz, T, u0, [gx * (1 + h), 0, 0], omega, **args)
+            - _fd_rollout(nx, ny, nz, T, u0, [gx * (1 - h), 0, 0], omega, **args)) / (2 * gx * h)
+    fd_w = (_fd_rollout(nx, ny, nz, T, u0, [gx, 0, 0], omega * (1 + h), **args)
+            - _fd_rollout(nx, ny, nz, T, u0, [gx, 0, 0], omega * (1 - h), **args)) / (2 * omega * h)
+    v = lbm_inputs.perturbation((nz, ny, nx), seed=10, amp=1.0)
+    hv = h * np.abs(u0).max()
+    fd_u = (_fd_rollout(nx, ny, nz, T, u0 + hv * v, [gx, 0, 0], omega, **args)
+            - _fd_rollout(nx, ny, nz, T, u0 - hv * v, [gx, 0, 0], omega, **args)) / (2 * hv)
+    g_u = float((host(u.grad) * v).sum())
+    rel = {"J": abs(J32.item() / J64 - 1), "gx": abs(a.grad[0].item() / fd_a - 1),
+           "omega": abs(w.grad.item() / fd_w - 1), "u_dir": abs(g_u / fd_u - 1)}
+    print("\nduct gradient FP32 adjoint vs FP64 central differences:",
+          json.dumps({"J64": J64, "dJ/dgx": [a.grad[0].item(), fd_a],
+                      "dJ/domega": [w.grad.item(), fd_w], "dJ/du.v": [g_u, fd_u],
+                      "rel_err": rel}))
+    # measured on MI355X: J 2.6e-5, g_x 2.1e-5, omega 1.5e-4, u 6.1e-5
+    assert rel["J"] < 2e-4
+    assert rel["gx"] < 1e-3 and rel["omega"] < 1e-3 and rel["u_dir"] < 1e-3
+
+
+def test_tube_192x192x768_trt_fp16_gradient():
+    """Constricted tube 768 x 192 x 192 (r(x) = 80 (1 - 0.5 exp(-((x - 384)/60)^2))),
+    D3Q19-I TRT, omega = 1.95, g_x = 2e-6, FP16 shifted forward storage,
+    FP32 adjoint, T = 2000 with ceil(sqrt(T)) = 45-step segments.  Outlet-flux
+    gradient with respect to g_x and a per-cell initial velocity perturbation
+    (at zero perturbation), against central differences of FP64 runs."""
+    from paper_1803_04937_amd import RolloutConfig, rollout_objective
+    nx, ny, nz, T = 768, 192, 192, 2000
+    gx, omega = 2e-6, 1.95
+    solid = lbm_inputs.tube_mask(nx, ny, nz, r0=80.0, depth=0.5, centre=384.0, width=60.0)
+    sd = dev(solid, torch.uint8)
+    u0 = np.zeros((3, nz, ny, nx))
+    rc = RolloutConfig(nx, ny, nz, steps=T, periodic=(1, 1, 1), collision="trt", dtype="f16s",
+                       objective=1, solid=sd)
+    assert rc.segment == 45
+    u = dev(u0).requires_grad_(True)
+    a = torch.tensor([gx, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    w = torch.tensor(omega, dtype=torch.float64, requires_grad=True)
+    J16 = rollout_objective(u, a, w, rc)
+    J16.backward()
+    h = 1e-4
+    args = dict(kind=1, periodic=(1, 1, 1), collision="trt", solid=sd)
+    J64 = _fd_rollout(nx, ny, nz, T, u0, [gx, 0, 0], omega, **args)
+    fd_a = (_fd_rollout(nx, ny, nz, T, u0, [gx * (1 + h), 0, 0], omega, **args)
+            - _fd_rollout(nx, ny, nz, T, u0, [gx * (1 - h), 0, 0], omega, **args)) / (2 * gx * h)
+    v = lbm_inputs.perturbation((nz, ny, nx), seed=11, amp=1.0) * (solid == 0)
+    hv = 1e-6
+    fd_u = (_fd_rollout(nx, ny, nz, T, hv * v, [gx, 0, 0], omega, **args)
+            - _fd_rollout(nx, ny, nz, T, -hv * v, [gx, 0, 0], omega, **args)) / (2 * hv)
+    g_u = float((host(u.grad) * v).sum())
+    rel = {"J": abs(J16.item() / J64 - 1), "gx": abs(a.grad[0].item() / fd_a - 1),
+           "u_dir": abs(g_u / fd_u - 1)}
+    print("\ntube gradient FP16-forward adjoint vs FP64 central differences:",
+          json.dumps({"J16": J16.item(), "J64": J64, "dJ/dgx": [a.grad[0].item(), fd_a],
+                      "dJ/du.v": [g_u, fd_u], "rel_err": rel}))
+    # measured on MI355X: J 1.4e-4, g_x 3.1e-5, u 1.7e-3
+    assert np.isfinite(a.grad.cpu().numpy()).all() and np.isfinite(host(u.grad)).all()
+    assert rel["J"] < 2e-3 and rel["gx"] < 2e-3 and rel["u_dir"] < 1e-2

@@ -23,18 +23,21 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The pin suite can be pointed at another build of oracle.c (a deliberately
+# broken copy, to show that the pins catch the mistake).
+_LIB_OVERRIDE = os.environ.get("LBM_ORACLE_LIB")
 
 NQ = 19
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc into liboracle.so (in-tree)."""
-    if force or not os.path.exists(_LIB):
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
+    """Compile oracle.c (or another source) with gcc into a shared library."""
+    if force or not os.path.exists(out):
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared",
-               "-fPIC", "-std=c99", _SRC, "-o", _LIB + ".tmp", "-lm"]
+               "-fPIC", "-std=c99", src, "-o", out + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 class _Cfg(ctypes.Structure):
@@ -53,9 +56,10 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = _LIB_OVERRIDE or _LIB
+        if not _LIB_OVERRIDE and not os.path.exists(_LIB):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         cfgp = ctypes.POINTER(_Cfg)
         lib.oracle_velocity_set.argtypes = [P, P, P]

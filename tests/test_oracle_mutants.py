@@ -1,0 +1,72 @@
+"""The oracle's pins catch plausible mistakes (CPU only).
+
+Each case plants one mistake in a copy of oracle/oracle.c (a wrong
+coefficient, sign, index, weight or transposed operand), builds it into a
+separate library and runs the oracle pin suite against that library in a
+fresh process: the suite must fail.  The unmodified oracle passes the same
+suite (the other test files).
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+PIN_FILES = ["tests/test_oracle_equilibrium.py", "tests/test_oracle_step.py",
+             "tests/test_oracle_adjoint.py"]
+
+MUTANTS = [
+    ("standard: 9/2 -> 4", "(3.0 * first + 4.5 * second)", "(3.0 * first + 4.0 * second)"),
+    ("standard: trace term dropped", "(a == b ? 1.0 / 3.0 : 0.0)", "(a == b ? 0.0 : 0.0)"),
+    ("improved rest: -u^2 -> -3/2 u^2", "bracket = -uu;", "bracket = -1.5 * uu;"),
+    ("improved axis: 6 (c.u)^2 -> 9/2", "6.0 * cu * cu;", "4.5 * cu * cu;"),
+    ("improved edge: unsummed u^2", "3.0 * cu - 1.5 * uc2", "3.0 * cu - 1.5 * uu"),
+    ("edge weight 1/36 -> 1/18", "return 1.0 / 36.0;", "return 1.0 / 18.0;"),
+    ("streaming sign", "int p[3] = {x + s * C[q][0],", "int p[3] = {x - s * C[q][0],"),
+    ("bounce-back reads own direction", "g[q] = f[(int64_t)opposite(q) * n + here];",
+     "g[q] = f[(int64_t)q * n + here];"),
+    ("velocity shift a/2 -> a", "u[d] = (j[d] + 0.5 * cfg->accel[d]) / *rho0;",
+     "u[d] = (j[d] + 1.0 * cfg->accel[d]) / *rho0;"),
+    ("SRT force factor (1 - w/2) -> (1 - w)",
+     "out[q] = g[q] - w * (g[q] - fe[q]) + (1.0 - w / 2.0) * force_term(cfg, q);",
+     "out[q] = g[q] - w * (g[q] - fe[q]) + (1.0 - w) * force_term(cfg, q);"),
+    ("TRT force relaxed with the even rate",
+     "out[q] = g[q] - w * (gp - ep) - wm * (gm - em) + (1.0 - wm / 2.0) * force_term(cfg, q);",
+     "out[q] = g[q] - w * (gp - ep) - wm * (gm - em) + (1.0 - w / 2.0) * force_term(cfg, q);"),
+    ("TRT Lambda inverted", "return 1.0 / (0.5 + cfg->magic / tau_plus);",
+     "return 1.0 / (0.5 + tau_plus / cfg->magic);"),
+    ("forcing weight / c_s^2 dropped", "return weight(q) / (1.0 / 3.0) * ca;",
+     "return weight(q) * ca;"),
+    ("read-out velocity shift dropped",
+     "u[d * n + c] = (j[d] - 0.5 * cfg->accel[d]) / rho0;", "u[d * n + c] = j[d] / rho0;"),
+    ("adjoint push to the opposite array", "lam_prev[(int64_t)r * n + src] = mu;",
+     "lam_prev[(int64_t)opposite(r) * n + src] = mu;"),
+    ("adjoint Jacobian transposed", "for (int r = 0; r < NQ; ++r) {\n            double v = weight(q);\n            for (int b = 0; b < 3; ++b) v += D[q][b] * C[r][b];",
+     "for (int r = 0; r < NQ; ++r) {\n            double v = weight(q);\n            for (int b = 0; b < 3; ++b) v += D[q][b] * C[q][b];"),
+    ("d feq/du improved axis 12 -> 9", "(3.0 * cb - 6.0 * u[b] + 12.0 * cu * cb)",
+     "(3.0 * cb - 6.0 * u[b] + 9.0 * cu * cb)"),
+    ("objective dJ/da sign", "da[d] += -0.5 * u[d];", "da[d] += 0.5 * u[d];"),
+    ("TRT d omega_minus / d omega sign",
+     "double dwm_dwp = -wm * wm * cfg->magic / (tau_p * tau_p * wp * wp);",
+     "double dwm_dwp = wm * wm * cfg->magic / (tau_p * tau_p * wp * wp);"),
+    ("init VJP reads the rest population only", "v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);",
+     "v += lam0[c] * dfeq_du(cfg, q, b, 1.0, u);"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique: {old!r}"
+    mutant = tmp_path / "oracle_mutant.c"
+    mutant.write_text(src.replace(old, new))
+    lib = oracle.build(force=True, src=str(mutant), out=str(tmp_path / "liboracle_mutant.so"))
+    env = dict(os.environ, LBM_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          *PIN_FILES], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=600)
+    assert res.returncode != 0, f"pins did not catch: {name}\n{res.stdout[-2000:]}"

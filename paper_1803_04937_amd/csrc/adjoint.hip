@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
                 bool fl;
                 const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
                 const typename S::T *p = state + (fl ? q : opp(q)) * g.qstride;
-                d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s);
+                d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s, nt_load_adj(kC[q].x));
                 lam[q] = (R)ld(lam_next + q * g.qstride + idx);
             }
             adjoint_cell<R, EQ>(d, lam, P, acc);
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
                 bool fl;
                 const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
                 L *p = lam_prev + (fl ? q : opp(q)) * g.qstride;
-                st(p + (fl ? c : idx), (L)lam[q]);
+                st(p + (fl ? c : idx), (L)lam[q], nt_store(kC[q].x));
             }
         }
     }

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
         const typename S::T *p = src + (fl ? q : opp(q)) * g.qstride;
-        d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s);
+        d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s, nt_load_fwd(kC[q].x));
     }
     collide<R, EQ>(d, P);
 #pragma unroll
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
         const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
-        d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s);
+        d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s, nt_load_fwd(kC[q].x));
     }
     collide<R, EQ>(d, P);
 #pragma unroll
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, +1, fl);
         typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
-        S::store(p, fl ? c : idx, d[q], (R)weight(q), P.s);
+        S::store(p, fl ? c : idx, d[q], (R)weight(q), P.s, nt_store(kC[q].x));
     }
 }
 

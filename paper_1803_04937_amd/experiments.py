@@ -1,0 +1,104 @@
+"""Duct-flow experiment of Sec. 5.1 on the GPU path: spurious transverse
+currents of the standard and the improved D3Q19 equilibrium.
+
+Set-up (Sec. 5.1): a square duct of D x D cells, one cell long and periodic
+along the flow axis x, half-way bounce-back walls on y and z, driven by the
+Buick body force along x, SRT collision with a fixed relaxation rate under
+diffusive scaling, Re = 10, run to a steady state.  Error measure:
+max |u_y| / max u_x.  Lambda = 1/omega - 1/2 (Sec. 4).
+
+Readings: Re = u_max D / nu with u_max the centre velocity of the
+square-duct Poiseuille solution, u_max = K a (D/2)^2 / nu, K = 0.29468...;
+the run starts from that solution and stops after `sweeps` viscous times
+D^2 / nu.
+
+Usage: python -m paper_1803_04937_amd.experiments [--dtype f64] [--sizes 15,25,45]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+
+import torch
+
+from .lattice import Lattice
+
+
+def _square_duct_centre_constant(nterms: int = 200) -> float:
+    """u(0, 0) a^-1 b^-2 nu of the square-duct Poiseuille series."""
+    s = 0.0
+    for m in range(nterms):
+        k = 2 * m + 1
+        s += (-1) ** m * (1.0 - 1.0 / math.cosh(k * math.pi / 2)) / k ** 3
+    return 16.0 / math.pi ** 3 * s
+
+
+K_CENTRE = _square_duct_centre_constant()
+
+
+def duct_spurious_current(D: int, lam2: float, equilibrium: str, dtype: str = "f64",
+                          re: float = 10.0, sweeps: float = 3.0, device=None) -> dict:
+    """Steady-state max |u_y| / max u_x of the duct for one resolution D,
+    one Lambda^2 and one equilibrium ("standard" or "improved")."""
+    import lbm_inputs
+    lam = math.sqrt(lam2)
+    omega = 1.0 / (lam + 0.5)
+    nu = lam / 3.0
+    a = re * nu * nu / (K_CENTRE * (D / 2.0) ** 2 * D)
+    u0 = torch.as_tensor(lbm_inputs.duct_poiseuille(1, D, D, a, nu))
+    lat = Lattice(1, D, D, u=u0, periodic=(1, 0, 0), equilibrium=equilibrium, collision="srt",
+                  dtype=dtype, omega=omega, accel=(a, 0.0, 0.0), device=device)
+    steps = int(math.ceil(sweeps * D * D / nu))
+    chunks = 10
+    per = max(1, steps // chunks)
+    history = []
+    for _ in range(chunks):
+        lat.step(per)
+        _, u = lat.moments()
+        ux = u[0].abs().max().item()
+        uy = torch.maximum(u[1].abs().max(), u[2].abs().max()).item()
+        history.append(uy / ux)
+    lat.close()
+    last, prev = history[-1], history[-2]
+    return {"D": D, "lambda2": lam2, "omega": omega, "equilibrium": equilibrium, "dtype": dtype,
+            "steps": per * chunks, "ratio": last, "ux_max": ux,
+            "last_chunk_rel_change": abs(last - prev) / max(abs(last), 1e-300)}
+
+
+def convergence_order(results):
+    """Least-squares slope of log(ratio) against log(D)."""
+    xs = [math.log(r["D"]) for r in results]
+    ys = [math.log(r["ratio"]) for r in results]
+    n = len(xs)
+    mx, my = sum(xs) / n, sum(ys) / n
+    return sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sum((x - mx) ** 2 for x in xs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dtype", default="f64")
+    ap.add_argument("--sizes", default="15,25,35,45,65")
+    ap.add_argument("--lambda2", default="0.16,0.0833333333333333")
+    ap.add_argument("--sweep", type=int, default=0,
+                    help="also sweep Lambda^2 at this D for the standard equilibrium")
+    a = ap.parse_args()
+    sizes = [int(v) for v in a.sizes.split(",")]
+    out = {}
+    for lam2 in [float(v) for v in a.lambda2.split(",")]:
+        for eq in ("standard", "improved"):
+            rows = [duct_spurious_current(D, lam2, eq, a.dtype) for D in sizes]
+            key = f"{eq}_lambda2={lam2:.4f}"
+            out[key] = {"rows": rows}
+            if eq == "standard":
+                out[key]["order"] = convergence_order(rows)
+            print(json.dumps({key: out[key]}), flush=True)
+    if a.sweep:
+        lams = [0.01, 0.02, 0.04, 0.06, 1.0 / 12.0, 0.1, 0.12, 0.16, 0.25]
+        sweep = [(l2, duct_spurious_current(a.sweep, l2, "standard", a.dtype)["ratio"])
+                 for l2 in lams]
+        print(json.dumps({f"standard_sweep_D={a.sweep}": sweep}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

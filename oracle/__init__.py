@@ -47,6 +47,7 @@ class _Cfg(ctypes.Structure):
         ("improved", ctypes.c_int), ("trt", ctypes.c_int), ("compressible", ctypes.c_int),
         ("omega", ctypes.c_double), ("magic", ctypes.c_double),
         ("accel", ctypes.c_double * 3),
+        ("stencil", ctypes.c_int),
     ]
 
 
@@ -62,7 +63,7 @@ def _load():
         lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         cfgp = ctypes.POINTER(_Cfg)
-        lib.oracle_velocity_set.argtypes = [P, P, P]
+        lib.oracle_velocity_set.argtypes = [ctypes.c_int, P, P, P]
         lib.oracle_feq.argtypes = [cfgp, ctypes.c_double, ctypes.c_double, P, P]
         lib.oracle_dfeq_du.argtypes = [cfgp, ctypes.c_double, P, P]
         lib.oracle_init.argtypes = [cfgp, P, P, P, P]
@@ -104,10 +105,15 @@ class Config:
     magic: float = 3.0 / 16.0
     accel: tuple = (0.0, 0.0, 0.0)
     solid: np.ndarray | None = field(default=None, repr=False)
+    stencil: int = 19
 
     @property
     def shape(self):
         return (self.nz, self.ny, self.nx)
+
+    @property
+    def q(self):
+        return 27 if self.stencil == 27 else 19
 
     @property
     def ncells(self):
@@ -124,6 +130,7 @@ class Config:
         c.compressible = int(self.compressible)
         c.omega = float(self.omega)
         c.magic = float(self.magic)
+        c.stencil = int(self.stencil)
         return ctypes.byref(c), c
 
     def _solid(self):
@@ -134,13 +141,14 @@ class Config:
         return s
 
 
-def velocity_set():
-    """(c [19,3] int, w [19] float, opposite [19] int) as the oracle encodes them."""
+def velocity_set(stencil: int = 19):
+    """(c [Q,3] int, w [Q] float, opposite [Q] int) as the oracle encodes them."""
     lib = _load()
-    c = np.zeros((NQ, 3), dtype=np.int32)
-    w = np.zeros(NQ, dtype=np.float64)
-    o = np.zeros(NQ, dtype=np.int32)
-    lib.oracle_velocity_set(_ptr(c), _ptr(w), _ptr(o))
+    qn = 27 if stencil == 27 else 19
+    c = np.zeros((qn, 3), dtype=np.int32)
+    w = np.zeros(qn, dtype=np.float64)
+    o = np.zeros(qn, dtype=np.int32)
+    lib.oracle_velocity_set(int(stencil), _ptr(c), _ptr(w), _ptr(o))
     return c.astype(np.int64), w, o.astype(np.int64)
 
 
@@ -150,7 +158,7 @@ def feq(cfg: Config, rho: float, u, rho0: float | None = None):
     if rho0 is None:
         rho0 = rho if cfg.compressible else 1.0
     uu = _f64(u, (3,))
-    out = np.zeros(NQ)
+    out = np.zeros(cfg.q)
     ref, _keep = cfg._c()
     lib.oracle_feq(ref, float(rho), float(rho0), _ptr(uu), _ptr(out))
     return out
@@ -159,7 +167,7 @@ def feq(cfg: Config, rho: float, u, rho0: float | None = None):
 def dfeq_du(cfg: Config, u, rho0: float = 1.0):
     lib = _load()
     uu = _f64(u, (3,))
-    out = np.zeros((NQ, 3))
+    out = np.zeros((cfg.q, 3))
     ref, _keep = cfg._c()
     lib.oracle_dfeq_du(ref, float(rho0), _ptr(uu), _ptr(out))
     return out
@@ -170,7 +178,7 @@ def init(cfg: Config, u, rho=None):
     lib = _load()
     u = _f64(u, (3,) + cfg.shape)
     r = None if rho is None else _f64(rho, cfg.shape)
-    f = np.empty((NQ,) + cfg.shape)
+    f = np.empty((cfg.q,) + cfg.shape)
     ref, _keep = cfg._c()
     lib.oracle_init(ref, _ptr(cfg._solid()), _ptr(r), _ptr(u), _ptr(f))
     return f
@@ -179,7 +187,7 @@ def init(cfg: Config, u, rho=None):
 def step(cfg: Config, f, nsteps: int = 1):
     """Advance a copy of f by nsteps two-grid pull steps; returns the result."""
     lib = _load()
-    f = _f64(f, (NQ,) + cfg.shape).copy()
+    f = _f64(f, (cfg.q,) + cfg.shape).copy()
     tmp = np.empty_like(f)
     ref, _keep = cfg._c()
     lib.oracle_run(ref, _ptr(cfg._solid()), _ptr(f), _ptr(tmp), int(nsteps))
@@ -189,9 +197,9 @@ def step(cfg: Config, f, nsteps: int = 1):
 def step_cells(cfg: Config, f, cells):
     """Post-step PDFs at the listed flat cell indices: array (len(cells), 19)."""
     lib = _load()
-    f = _f64(f, (NQ,) + cfg.shape)
+    f = _f64(f, (cfg.q,) + cfg.shape)
     cells = np.ascontiguousarray(cells, dtype=np.int64)
-    out = np.empty((cells.size, NQ))
+    out = np.empty((cells.size, cfg.q))
     ref, _keep = cfg._c()
     lib.oracle_step_cells(ref, _ptr(cfg._solid()), _ptr(f), _ptr(cells), cells.size, _ptr(out))
     return out
@@ -200,7 +208,7 @@ def step_cells(cfg: Config, f, cells):
 def moments(cfg: Config, f):
     """(rho (nz,ny,nx), u (3,nz,ny,nx)) of a stored post-collision state."""
     lib = _load()
-    f = _f64(f, (NQ,) + cfg.shape)
+    f = _f64(f, (cfg.q,) + cfg.shape)
     rho = np.empty(cfg.shape)
     u = np.empty((3,) + cfg.shape)
     ref, _keep = cfg._c()

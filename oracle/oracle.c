@@ -13,10 +13,13 @@
  * cell = (z * ny + y) * nx + x (x fastest).  All arithmetic is FP64.
  *
  * What each function follows:
- *   velocity set, weights ........ Sec. 2.3 (D3Q19 stencil and weights)
+ *   velocity sets, weights ....... Sec. 2.3 (D3Q19 and D3Q27 stencils, weights)
  *   standard equilibrium ......... Sec. 2.2, eq. discreteEquilibriumStandard,
  *                                  second-order part, rho0 from Sec. 2.3
  *   improved equilibrium ......... Sec. 3.2, eq. new_d3q19_equilibrium
+ *   D3Q27 equilibrium ............ Sec. 3.1: moment matching on D3Q27 gives
+ *                                  the standard equilibrium with D3Q27
+ *                                  weights, so D3Q27 uses that form
  *   forcing term ................. Sec. 2.3, F_q = w_q / c_s^2 c_q . a
  *   SRT update ................... Sec. 2.3, eq. lb_srt_with_forces
  *   macroscopic moments .......... Sec. 2.3, eqs. mass_conservation and
@@ -42,11 +45,12 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define NQ 19
+#define NQ 27 /* array bound: D3Q27; D3Q19 uses the first 19 entries */
 
 /* ------------------------------------------------------------------------ */
-/* Velocity set (Sec. 2.3).  Order: rest; the six axis directions; the       */
-/* twelve edge directions; opposite directions sit next to each other.       */
+/* Velocity sets (Sec. 2.3).  Order: rest; the six axis directions; the      */
+/* twelve edge directions (D3Q19 ends here); the eight corner directions     */
+/* (D3Q27).  Opposite directions sit next to each other.                     */
 /* ------------------------------------------------------------------------ */
 static const int C[NQ][3] = {
     {0, 0, 0},
@@ -54,16 +58,12 @@ static const int C[NQ][3] = {
     {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
     {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
     {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1},
 };
 
-/* Weights by the squared length of c_q (Sec. 2.3): 1/3, 1/18, 1/36. */
-static double weight(int q)
-{
-    int n2 = C[q][0] * C[q][0] + C[q][1] * C[q][1] + C[q][2] * C[q][2];
-    if (n2 == 0) return 1.0 / 3.0;
-    if (n2 == 1) return 1.0 / 18.0;
-    return 1.0 / 36.0;
-}
+/* Number of directions of the configured stencil. */
+#define QN(cfg) ((cfg)->stencil == 27 ? 27 : 19)
 
 /* The direction with c_p = -c_q, found by search. */
 static int opposite(int q)
@@ -82,13 +82,32 @@ typedef struct {
     double omega;       /* SRT rate, or TRT even rate omega_plus             */
     double magic;       /* TRT Lambda = (1/w+ - 1/2)(1/w- - 1/2)             */
     double accel[3];    /* body acceleration a                               */
+    int stencil;        /* 19 (D3Q19) or 27 (D3Q27)                          */
 } oracle_cfg;
 
-void oracle_velocity_set(int *c_out, double *w_out, int *opp_out)
+/* Weights by the squared length of c_q (Sec. 2.3).  D3Q19: 1/3, 1/18, 1/36.
+ * D3Q27: 8/27, 2/27, 1/54, 1/216. */
+static double weight_of(int stencil, int q)
 {
-    for (int q = 0; q < NQ; ++q) {
+    int n2 = C[q][0] * C[q][0] + C[q][1] * C[q][1] + C[q][2] * C[q][2];
+    if (stencil == 27) {
+        if (n2 == 0) return 8.0 / 27.0;
+        if (n2 == 1) return 2.0 / 27.0;
+        if (n2 == 2) return 1.0 / 54.0;
+        return 1.0 / 216.0;
+    }
+    if (n2 == 0) return 1.0 / 3.0;
+    if (n2 == 1) return 1.0 / 18.0;
+    return 1.0 / 36.0;
+}
+#define weight(q) weight_of(cfg->stencil, (q))
+
+void oracle_velocity_set(int stencil, int *c_out, double *w_out, int *opp_out)
+{
+    int qn = stencil == 27 ? 27 : 19;
+    for (int q = 0; q < qn; ++q) {
         for (int d = 0; d < 3; ++d) c_out[3 * q + d] = C[q][d];
-        w_out[q] = weight(q);
+        w_out[q] = weight_of(stencil, q);
         opp_out[q] = opposite(q);
     }
 }
@@ -99,7 +118,8 @@ void oracle_velocity_set(int *c_out, double *w_out, int *opp_out)
 
 /* Standard equilibrium: w rho + w rho0 [3 c_a u_a
  *                                      + 9/2 u_a u_b (c_a c_b - delta_ab/3)]. */
-static double feq_standard(int q, double rho, double rho0, const double u[3])
+static double feq_standard(const oracle_cfg *cfg, int q, double rho, double rho0,
+                           const double u[3])
 {
     double first = 0.0, second = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -112,7 +132,8 @@ static double feq_standard(int q, double rho, double rho0, const double u[3])
 
 /* Improved equilibrium D3Q19-I, case by case on the type of c_q.  The edge
  * term -3/2 u_i^2 c_qi^2 is summed over i. */
-static double feq_improved(int q, double rho, double rho0, const double u[3])
+static double feq_improved(const oracle_cfg *cfg, int q, double rho, double rho0,
+                           const double u[3])
 {
     int n2 = C[q][0] * C[q][0] + C[q][1] * C[q][1] + C[q][2] * C[q][2];
     double cu = 0.0, uu = 0.0, uc2 = 0.0;
@@ -133,7 +154,8 @@ static double feq_improved(int q, double rho, double rho0, const double u[3])
 
 static double feq(const oracle_cfg *cfg, int q, double rho, double rho0, const double u[3])
 {
-    return cfg->improved ? feq_improved(q, rho, rho0, u) : feq_standard(q, rho, rho0, u);
+    if (cfg->stencil == 27) return feq_standard(cfg, q, rho, rho0, u);
+    return cfg->improved ? feq_improved(cfg, q, rho, rho0, u) : feq_standard(cfg, q, rho, rho0, u);
 }
 
 /* d f^eq_q / d u_b at fixed rho and rho0, differentiated by hand from the two
@@ -143,7 +165,7 @@ static double dfeq_du(const oracle_cfg *cfg, int q, int b, double rho0, const do
     double cu = 0.0;
     for (int i = 0; i < 3; ++i) cu += u[i] * C[q][i];
     double cb = C[q][b];
-    if (!cfg->improved)
+    if (!cfg->improved || cfg->stencil == 27)
         return weight(q) * rho0 * (3.0 * cb + 9.0 * cu * cb - 3.0 * u[b]);
     int n2 = C[q][0] * C[q][0] + C[q][1] * C[q][1] + C[q][2] * C[q][2];
     if (n2 == 0) return weight(q) * rho0 * (-2.0 * u[b]);
@@ -153,12 +175,12 @@ static double dfeq_du(const oracle_cfg *cfg, int q, int b, double rho0, const do
 
 void oracle_feq(const oracle_cfg *cfg, double rho, double rho0, const double *u, double *out)
 {
-    for (int q = 0; q < NQ; ++q) out[q] = feq(cfg, q, rho, rho0, u);
+    for (int q = 0; q < QN(cfg); ++q) out[q] = feq(cfg, q, rho, rho0, u);
 }
 
 void oracle_dfeq_du(const oracle_cfg *cfg, double rho0, const double *u, double *out /*[19][3]*/)
 {
-    for (int q = 0; q < NQ; ++q)
+    for (int q = 0; q < QN(cfg); ++q)
         for (int b = 0; b < 3; ++b) out[3 * q + b] = dfeq_du(cfg, q, b, rho0, u);
 }
 
@@ -213,7 +235,7 @@ static void gather(const oracle_cfg *cfg, const uint8_t *solid, const double *f,
 {
     int64_t n = ncells_of(cfg);
     int64_t here = ((int64_t)z * cfg->ny + y) * cfg->nx + x;
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < QN(cfg); ++q) {
         int64_t src = shifted_cell(cfg, x, y, z, q, -1);
         if (is_solid(solid, src))
             g[q] = f[(int64_t)opposite(q) * n + here];
@@ -227,7 +249,7 @@ static void macroscopic(const oracle_cfg *cfg, const double g[NQ], double *rho, 
                         double u[3])
 {
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < QN(cfg); ++q) {
         r += g[q];
         for (int d = 0; d < 3; ++d) j[d] += C[q][d] * g[q];
     }
@@ -241,15 +263,15 @@ static void collide(const oracle_cfg *cfg, const double g[NQ], double out[NQ])
 {
     double rho, rho0, u[3], fe[NQ];
     macroscopic(cfg, g, &rho, &rho0, u);
-    for (int q = 0; q < NQ; ++q) fe[q] = feq(cfg, q, rho, rho0, u);
+    for (int q = 0; q < QN(cfg); ++q) fe[q] = feq(cfg, q, rho, rho0, u);
     double w = cfg->omega;
     if (!cfg->trt) {
-        for (int q = 0; q < NQ; ++q)
+        for (int q = 0; q < QN(cfg); ++q)
             out[q] = g[q] - w * (g[q] - fe[q]) + (1.0 - w / 2.0) * force_term(cfg, q);
         return;
     }
     double wm = omega_minus(cfg);
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < QN(cfg); ++q) {
         int qb = opposite(q);
         double gp = 0.5 * (g[q] + g[qb]), gm = 0.5 * (g[q] - g[qb]);
         double ep = 0.5 * (fe[q] + fe[qb]), em = 0.5 * (fe[q] - fe[qb]);
@@ -270,13 +292,13 @@ void oracle_init(const oracle_cfg *cfg, const uint8_t *solid, const double *rho_
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
         if (solid && solid[c]) {
-            for (int q = 0; q < NQ; ++q) f[q * n + c] = weight(q);
+            for (int q = 0; q < QN(cfg); ++q) f[q * n + c] = weight(q);
             continue;
         }
         double u[3] = {u_init[c], u_init[n + c], u_init[2 * n + c]};
         double rho = rho_init ? rho_init[c] : 1.0;
         double rho0 = cfg->compressible ? rho : 1.0;
-        for (int q = 0; q < NQ; ++q) f[q * n + c] = feq(cfg, q, rho, rho0, u);
+        for (int q = 0; q < QN(cfg); ++q) f[q * n + c] = feq(cfg, q, rho, rho0, u);
     }
 }
 
@@ -290,19 +312,19 @@ void oracle_step(const oracle_cfg *cfg, const uint8_t *solid, const double *fin,
             for (int x = 0; x < cfg->nx; ++x) {
                 int64_t c = ((int64_t)z * cfg->ny + y) * cfg->nx + x;
                 if (solid && solid[c]) {
-                    for (int q = 0; q < NQ; ++q) fout[q * n + c] = fin[q * n + c];
+                    for (int q = 0; q < QN(cfg); ++q) fout[q * n + c] = fin[q * n + c];
                     continue;
                 }
                 double g[NQ], out[NQ];
                 gather(cfg, solid, fin, x, y, z, g);
                 collide(cfg, g, out);
-                for (int q = 0; q < NQ; ++q) fout[q * n + c] = out[q];
+                for (int q = 0; q < QN(cfg); ++q) fout[q * n + c] = out[q];
             }
 }
 
 void oracle_run(const oracle_cfg *cfg, const uint8_t *solid, double *f, double *tmp, int nsteps)
 {
-    int64_t bytes = ncells_of(cfg) * NQ * (int64_t)sizeof(double);
+    int64_t bytes = ncells_of(cfg) * QN(cfg) * (int64_t)sizeof(double);
     for (int s = 0; s < nsteps; ++s) {
         oracle_step(cfg, solid, f, tmp);
         memcpy(f, tmp, (size_t)bytes);
@@ -321,12 +343,12 @@ void oracle_step_cells(const oracle_cfg *cfg, const uint8_t *solid, const double
         int x = (int)(c % cfg->nx), y = (int)((c / cfg->nx) % cfg->ny),
             z = (int)(c / ((int64_t)cfg->nx * cfg->ny));
         if (solid && solid[c]) {
-            for (int q = 0; q < NQ; ++q) out[k * NQ + q] = fin[q * n + c];
+            for (int q = 0; q < QN(cfg); ++q) out[k * QN(cfg) + q] = fin[q * n + c];
             continue;
         }
         double g[NQ];
         gather(cfg, solid, fin, x, y, z, g);
-        collide(cfg, g, out + k * NQ);
+        collide(cfg, g, out + k * QN(cfg));
     }
 }
 
@@ -344,7 +366,7 @@ void oracle_moments(const oracle_cfg *cfg, const uint8_t *solid, const double *f
             continue;
         }
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < NQ; ++q) {
+        for (int q = 0; q < QN(cfg); ++q) {
             r += f[q * n + c];
             for (int d = 0; d < 3; ++d) j[d] += C[q][d] * f[q * n + c];
         }
@@ -365,13 +387,13 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
 {
     double rho, rho0, u[3], fe[NQ], D[NQ][3], dfe_dg[NQ][NQ];
     macroscopic(cfg, g, &rho, &rho0, u);
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < QN(cfg); ++q) {
         fe[q] = feq(cfg, q, rho, rho0, u);
         for (int b = 0; b < 3; ++b) D[q][b] = dfeq_du(cfg, q, b, rho0, u);
     }
     /* With rho0 = 1: d rho / d g_r = 1, d u_b / d g_r = c_rb, d u_b / d a_b = 1/2. */
-    for (int q = 0; q < NQ; ++q)
-        for (int r = 0; r < NQ; ++r) {
+    for (int q = 0; q < QN(cfg); ++q)
+        for (int r = 0; r < QN(cfg); ++r) {
             double v = weight(q);
             for (int b = 0; b < 3; ++b) v += D[q][b] * C[r][b];
             dfe_dg[q][r] = v;
@@ -379,28 +401,28 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
     double wp = cfg->omega, wm = omega_minus(cfg);
     /* Relaxation matrix R = wp P+ + wm P-, P+- = (I +- reversal) / 2. */
     double R[NQ][NQ];
-    for (int q = 0; q < NQ; ++q)
-        for (int s = 0; s < NQ; ++s) {
+    for (int q = 0; q < QN(cfg); ++q)
+        for (int s = 0; s < QN(cfg); ++s) {
             double pp = 0.5 * ((q == s) + (opposite(q) == s));
             double pm = 0.5 * ((q == s) - (opposite(q) == s));
             R[q][s] = cfg->trt ? wp * pp + wm * pm : wp * (q == s);
         }
-    for (int q = 0; q < NQ; ++q)
-        for (int r = 0; r < NQ; ++r) {
+    for (int q = 0; q < QN(cfg); ++q)
+        for (int r = 0; r < QN(cfg); ++r) {
             double v = (q == r) - R[q][r];
-            for (int s = 0; s < NQ; ++s) v += R[q][s] * dfe_dg[s][r];
+            for (int s = 0; s < QN(cfg); ++s) v += R[q][s] * dfe_dg[s][r];
             J[q][r] = v;
         }
     double fm = cfg->trt ? wm : wp; /* rate multiplying the force */
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < QN(cfg); ++q) {
         for (int b = 0; b < 3; ++b) {
             double v = 0.0;
-            for (int s = 0; s < NQ; ++s) v += R[q][s] * 0.5 * D[s][b];
+            for (int s = 0; s < QN(cfg); ++s) v += R[q][s] * 0.5 * D[s][b];
             da[q][b] = v + (1.0 - fm / 2.0) * 3.0 * weight(q) * C[q][b];
         }
     }
     /* d f* / d omega.  For TRT, omega_minus follows omega through fixed Lambda. */
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < QN(cfg); ++q) {
         int qb = opposite(q);
         if (!cfg->trt) {
             dw[q] = -(g[q] - fe[q]) - 0.5 * force_term(cfg, q);
@@ -418,11 +440,11 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
 
 /* lam_prev = (d step / d f_t)^T lam_next.  grad[0] += dJ/domega,
  * grad[1..3] += dJ/da (the contribution of this step).  Returns -1 for the
- * compressible form, which has no adjoint here. */
+ * compressible form and for D3Q27, which have no adjoint here. */
 int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const double *f_t,
                         const double *lam_next, double *lam_prev, double *grad)
 {
-    if (cfg->compressible) return -1;
+    if (cfg->compressible || cfg->stencil == 27) return -1;
     int64_t n = ncells_of(cfg);
     double *plane = (double *)calloc((size_t)cfg->nz * 4, sizeof(double));
 #pragma omp parallel for schedule(static)
@@ -432,22 +454,22 @@ int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const doubl
             for (int x = 0; x < cfg->nx; ++x) {
                 int64_t c = ((int64_t)z * cfg->ny + y) * cfg->nx + x;
                 if (solid && solid[c]) {
-                    for (int q = 0; q < NQ; ++q) lam_prev[q * n + c] = lam_next[q * n + c];
+                    for (int q = 0; q < QN(cfg); ++q) lam_prev[q * n + c] = lam_next[q * n + c];
                     continue;
                 }
                 double g[NQ], J[NQ][NQ], dw[NQ], da[NQ][3], lam[NQ];
                 gather(cfg, solid, f_t, x, y, z, g);
                 collision_jacobian(cfg, g, J, dw, da);
-                for (int q = 0; q < NQ; ++q) lam[q] = lam_next[q * n + c];
-                for (int q = 0; q < NQ; ++q) {
+                for (int q = 0; q < QN(cfg); ++q) lam[q] = lam_next[q * n + c];
+                for (int q = 0; q < QN(cfg); ++q) {
                     acc[0] += lam[q] * dw[q];
                     for (int b = 0; b < 3; ++b) acc[1 + b] += lam[q] * da[q][b];
                 }
                 /* mu = J^T lam, pushed back along the pull: g_r(x) was read
                  * from f_r(x - c_r), or from f_rbar(x) at a wall. */
-                for (int r = 0; r < NQ; ++r) {
+                for (int r = 0; r < QN(cfg); ++r) {
                     double mu = 0.0;
-                    for (int q = 0; q < NQ; ++q) mu += J[q][r] * lam[q];
+                    for (int q = 0; q < QN(cfg); ++q) mu += J[q][r] * lam[q];
                     int64_t src = shifted_cell(cfg, x, y, z, r, -1);
                     if (is_solid(solid, src))
                         lam_prev[(int64_t)opposite(r) * n + c] = mu;
@@ -477,12 +499,12 @@ double oracle_objective(const oracle_cfg *cfg, const uint8_t *solid, int kind, c
         int fluid = !(solid && solid[c]);
         double u[3] = {0.0, 0.0, 0.0};
         if (fluid) {
-            for (int q = 0; q < NQ; ++q)
+            for (int q = 0; q < QN(cfg); ++q)
                 for (int d = 0; d < 3; ++d) u[d] += C[q][d] * f[q * n + c];
             for (int d = 0; d < 3; ++d) u[d] -= 0.5 * cfg->accel[d];
         }
         int on_outlet = (int)(c % cfg->nx) == cfg->nx - 1;
-        for (int q = 0; q < NQ; ++q) {
+        for (int q = 0; q < QN(cfg); ++q) {
             double s = 0.0;
             if (fluid && kind == 0)
                 s = C[q][0] * u[0] + C[q][1] * u[1] + C[q][2] * u[2];
@@ -519,7 +541,7 @@ void oracle_init_vjp(const oracle_cfg *cfg, const uint8_t *solid, const double *
         double u[3] = {u_init[c], u_init[n + c], u_init[2 * n + c]};
         for (int b = 0; b < 3; ++b) {
             double v = 0.0;
-            for (int q = 0; q < NQ; ++q) v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);
+            for (int q = 0; q < QN(cfg); ++q) v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);
             grad_u[b * n + c] = v;
         }
     }

@@ -17,7 +17,7 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_FILES = ["tests/test_oracle_equilibrium.py", "tests/test_oracle_step.py",
-             "tests/test_oracle_adjoint.py"]
+             "tests/test_oracle_adjoint.py", "tests/test_oracle_d3q27.py"]
 
 MUTANTS = [
     ("standard: 9/2 -> 4", "(3.0 * first + 4.5 * second)", "(3.0 * first + 4.0 * second)"),
@@ -45,14 +45,18 @@ MUTANTS = [
      "u[d * n + c] = (j[d] - 0.5 * cfg->accel[d]) / rho0;", "u[d * n + c] = j[d] / rho0;"),
     ("adjoint push to the opposite array", "lam_prev[(int64_t)r * n + src] = mu;",
      "lam_prev[(int64_t)opposite(r) * n + src] = mu;"),
-    ("adjoint Jacobian transposed", "for (int r = 0; r < NQ; ++r) {\n            double v = weight(q);\n            for (int b = 0; b < 3; ++b) v += D[q][b] * C[r][b];",
-     "for (int r = 0; r < NQ; ++r) {\n            double v = weight(q);\n            for (int b = 0; b < 3; ++b) v += D[q][b] * C[q][b];"),
+    ("adjoint Jacobian transposed", "for (int r = 0; r < QN(cfg); ++r) {\n            double v = weight(q);\n            for (int b = 0; b < 3; ++b) v += D[q][b] * C[r][b];",
+     "for (int r = 0; r < QN(cfg); ++r) {\n            double v = weight(q);\n            for (int b = 0; b < 3; ++b) v += D[q][b] * C[q][b];"),
     ("d feq/du improved axis 12 -> 9", "(3.0 * cb - 6.0 * u[b] + 12.0 * cu * cb)",
      "(3.0 * cb - 6.0 * u[b] + 9.0 * cu * cb)"),
     ("objective dJ/da sign", "da[d] += -0.5 * u[d];", "da[d] += 0.5 * u[d];"),
     ("TRT d omega_minus / d omega sign",
      "double dwm_dwp = -wm * wm * cfg->magic / (tau_p * tau_p * wp * wp);",
      "double dwm_dwp = wm * wm * cfg->magic / (tau_p * tau_p * wp * wp);"),
+    ("D3Q27 corner weight 1/216 -> 1/108", "return 1.0 / 216.0;", "return 1.0 / 108.0;"),
+    ("D3Q27 takes the D3Q19-I form",
+     "if (cfg->stencil == 27) return feq_standard(cfg, q, rho, rho0, u);",
+     "if (cfg->stencil == 27) return feq_improved(cfg, q, rho, rho0, u);"),
     ("init VJP reads the rest population only", "v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);",
      "v += lam0[c] * dfeq_du(cfg, q, b, 1.0, u);"),
 ]

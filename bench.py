@@ -213,6 +213,16 @@ def main():
                                    "mlups": round(ncells / (ms * 1e-3) / 1e6, 1)}
         lat2.close()
         del lat2
+        # D3Q27 (Sec. 1 and Sec. 6: D3Q19 moves 19/27 of the data)
+        lat2 = Lattice(n, n, n, u=u0, dtype="f32", stencil=27, **common)
+        ms27 = timed_forward(torch, lat2, 50, 5)
+        gbs = 2 * 27 * 4 * ncells / (ms27 * 1e-3) / 1e9
+        extras["fwd_f32_d3q27_trt"] = {
+            "ms": round(ms27, 5), "mlups": round(ncells / (ms27 * 1e-3) / 1e6, 1),
+            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "time_ratio_vs_d3q19": round(ms27 / fwd_ms, 3)}
+        lat2.close()
+        del lat2
     if copy_ms is not None:
         extras["copy_state_f32"] = {"ms": round(copy_ms, 5), "bytes": 2 * state_bytes,
                                     "GBs": round(2 * state_bytes / (copy_ms * 1e-3) / 1e9, 1)}

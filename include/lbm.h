@@ -1,5 +1,6 @@
 /*
- * lbm.h -- C ABI of the MI355X (gfx950) D3Q19 lattice Boltzmann library.
+ * lbm.h -- C ABI of the MI355X (gfx950) D3Q19 / D3Q27 lattice Boltzmann
+ * library.
  *
  * Method: Bauer & Ruede, "An improved lattice Boltzmann D3Q19 method based on
  * an alternative equilibrium discretization" (arXiv:1803.04937).
@@ -22,12 +23,16 @@
  *    7 ( 1, 1, 0)   8 (-1,-1, 0)   9 ( 1,-1, 0)  10 (-1, 1, 0)
  *   11 ( 1, 0, 1)  12 (-1, 0,-1)  13 ( 1, 0,-1)  14 (-1, 0, 1)
  *   15 ( 0, 1, 1)  16 ( 0,-1,-1)  17 ( 0, 1,-1)  18 ( 0,-1, 1)
- * with weights 1/3 (rest), 1/18 (axis), 1/36 (edge).
+ * with weights 1/3 (rest), 1/18 (axis), 1/36 (edge).  D3Q27 appends the
+ * eight corners
+ *   19 ( 1, 1, 1)  20 (-1,-1,-1)  21 ( 1, 1,-1)  22 (-1,-1, 1)
+ *   23 ( 1,-1, 1)  24 (-1, 1,-1)  25 (-1, 1, 1)  26 ( 1,-1,-1)
+ * with weights 8/27, 2/27, 1/54, 1/216 (rest, axis, edge, corner).
  *
  * Cells: (x, y, z), x fastest; cell index c = (z * ny + y) * nx + x.
  *
- * State buffer layout (lbm_state_bytes): structure of arrays,
- * element [q * qstride + c] of the storage type, qstride >= nx*ny*nz
+ * State buffer layout (lbm_state_bytes): structure of arrays of Q = 19 or 27
+ * directions, element [q * qstride + c] of the storage type, qstride >= nx*ny*nz
  * (padded; see lbm_qstride).  What an element holds depends on the dtype:
  *   LBM_F64, LBM_F32            f_q (post-collision)
  *   LBM_F32_SHIFTED             f_q - w_q
@@ -96,6 +101,9 @@ typedef struct {
     int32_t pattern;          /* LBM_TWO_GRID / LBM_AA                            */
     int32_t compressible;     /* 0: rho0 = 1 (the paper's choice); 1: rho0 = rho   */
     int32_t adjoint_dtype;    /* LBM_F64 (only with dtype LBM_F64) or LBM_F32      */
+    int32_t stencil;          /* 19 (D3Q19) or 27 (D3Q27; its single equilibrium
+                                 is the moment-matched = standard one, Sec. 3.1,
+                                 whatever `equilibrium` says; forward only)      */
     double omega;             /* SRT rate or TRT even rate, 0 < omega < 2         */
     double trt_magic;         /* TRT Lambda > 0; ignored for SRT                  */
     double accel[3];          /* body acceleration a; F_q = 3 w_q c_q.a (Sec. 2.3) */
@@ -106,8 +114,9 @@ typedef struct {
 /* Library version string. */
 const char *lbm_version(void);
 
-/* Velocity set as encoded in the library: c[19*3], w[19], opposite[19]. */
-void lbm_velocity_set(int32_t *c, double *w, int32_t *opposite);
+/* Velocity set as encoded in the library for stencil 19 or 27:
+ * c[Q*3], w[Q], opposite[Q]. */
+void lbm_velocity_set(int32_t stencil, int32_t *c, double *w, int32_t *opposite);
 
 /* Padded q-stride (elements) and bytes of one PDF state buffer, and bytes of
  * one adjoint field, for these parameters.  Host only; no GPU needed. */
@@ -173,11 +182,11 @@ double lbm_scale(const lbm_ctx *c);
  * (mass and momentum); a non-NULL sums synchronises the stream. */
 int lbm_moments(lbm_ctx *c, double *rho, double *u, double *sums);
 
-/* Canonical copy of the current state: device double [19][cells] (dense,
+/* Canonical copy of the current state: device double [Q][cells] (dense,
  * no padding), f*_q in FP64 whatever the dtype and AA parity. */
 int lbm_get_pdfs(lbm_ctx *c, double *canonical);
 
-/* Overwrite the current state from a canonical device double [19][cells]
+/* Overwrite the current state from a canonical device double [Q][cells]
  * (quantised with the context's scale).  Solid cells are set to w_q. */
 int lbm_set_pdfs(lbm_ctx *c, const double *canonical);
 
@@ -191,7 +200,8 @@ int lbm_set_rates(lbm_ctx *c, double omega, const double *accel);
 
 /* ------------------------------------------------------------------------ */
 /* Adjoint (not in the paper): exact transpose of one two-grid step.         */
-/* Incompressible form (compressible == 0) only.                             */
+/* D3Q19, incompressible form (compressible == 0) only; otherwise            */
+/* LBM_ESTATE.                                                               */
 /* ------------------------------------------------------------------------ */
 
 /* lam_prev = (d step / d f_t)^T lam_next for the step f_t -> f_{t+1}.

@@ -47,6 +47,7 @@ class lbm_params(ctypes.Structure):
         ("equilibrium", ctypes.c_int32), ("collision", ctypes.c_int32),
         ("dtype", ctypes.c_int32), ("pattern", ctypes.c_int32),
         ("compressible", ctypes.c_int32), ("adjoint_dtype", ctypes.c_int32),
+        ("stencil", ctypes.c_int32),
         ("omega", ctypes.c_double), ("trt_magic", ctypes.c_double),
         ("accel", ctypes.c_double * 3), ("scale", ctypes.c_double),
     ]
@@ -62,7 +63,7 @@ def _load():
     pp = ctypes.POINTER(lbm_params)
     sig = {
         "lbm_version": ([], ctypes.c_char_p),
-        "lbm_velocity_set": ([P, P, P], None),
+        "lbm_velocity_set": ([ctypes.c_int32, P, P, P], None),
         "lbm_qstride": ([pp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "lbm_state_bytes": ([pp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_adjoint_bytes": ([pp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -116,7 +117,8 @@ def _check(rc: int, ctx=None):
 
 def make_params(nx, ny, nz, periodic=(1, 1, 1), equilibrium=LBM_EQ_IMPROVED, collision=LBM_SRT,
                 dtype=LBM_F32, pattern=LBM_TWO_GRID, compressible=0, adjoint_dtype=None,
-                omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0), scale=0.0) -> lbm_params:
+                omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0), scale=0.0,
+                stencil=19) -> lbm_params:
     p = lbm_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     for d in range(3):
@@ -130,6 +132,7 @@ def make_params(nx, ny, nz, periodic=(1, 1, 1), equilibrium=LBM_EQ_IMPROVED, col
     if adjoint_dtype is None:
         adjoint_dtype = LBM_F64 if dtype == LBM_F64 else LBM_F32
     p.adjoint_dtype = int(adjoint_dtype)
+    p.stencil = int(stencil)
     p.omega = float(omega)
     p.trt_magic = float(trt_magic)
     p.scale = float(scale)
@@ -144,12 +147,14 @@ def lbm_version() -> str:
     return _lib.lbm_version().decode()
 
 
-def lbm_velocity_set():
-    c = (ctypes.c_int32 * 57)()
-    w = (ctypes.c_double * 19)()
-    o = (ctypes.c_int32 * 19)()
-    _lib.lbm_velocity_set(ctypes.addressof(c), ctypes.addressof(w), ctypes.addressof(o))
-    return ([tuple(c[3 * q:3 * q + 3]) for q in range(19)], list(w), list(o))
+def lbm_velocity_set(stencil: int = 19):
+    qn = 27 if stencil == 27 else 19
+    c = (ctypes.c_int32 * (3 * qn))()
+    w = (ctypes.c_double * qn)()
+    o = (ctypes.c_int32 * qn)()
+    _lib.lbm_velocity_set(int(stencil), ctypes.addressof(c), ctypes.addressof(w),
+                          ctypes.addressof(o))
+    return ([tuple(c[3 * q:3 * q + 3]) for q in range(qn)], list(w), list(o))
 
 
 def lbm_qstride(p: lbm_params) -> int:

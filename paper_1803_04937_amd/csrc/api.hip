@@ -48,16 +48,17 @@ static int hip_fail(lbm_ctx *c, hipError_t e, const char *where) {
     return fail(c, LBM_EHIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-extern "C" const char *lbm_version(void) { return "lbm-d3q19-gfx950 1.0"; }
+extern "C" const char *lbm_version(void) { return "lbm-d3q19-d3q27-gfx950 1.1"; }
 
-extern "C" void lbm_velocity_set(int32_t *c, double *w, int32_t *o) {
-    for (int q = 0; q < Q; ++q) {
+extern "C" void lbm_velocity_set(int32_t stencil, int32_t *c, double *w, int32_t *o) {
+    const int qn = stencil == 27 ? 27 : 19;
+    for (int q = 0; q < qn; ++q) {
         if (c) {
             c[3 * q + 0] = kC[q].x;
             c[3 * q + 1] = kC[q].y;
             c[3 * q + 2] = kC[q].z;
         }
-        if (w) w[q] = weight(q);
+        if (w) w[q] = wq(qn, q);
         if (o) o[q] = opp(q);
     }
 }
@@ -105,6 +106,10 @@ static int validate(const lbm_params *p, std::string &why) {
     }
     if (p->compressible != 0 && p->compressible != 1) {
         why = "compressible must be 0 or 1";
+        return LBM_EINVAL;
+    }
+    if (p->stencil != 19 && p->stencil != 27) {
+        why = "stencil must be 19 or 27";
         return LBM_EINVAL;
     }
     const int want_lt = p->dtype == LBM_F64 ? LBM_F64 : LBM_F32;
@@ -169,7 +174,7 @@ extern "C" int lbm_qstride(const lbm_params *p, int64_t *qs) {
 extern "C" int lbm_state_bytes(const lbm_params *p, size_t *bytes) {
     std::string why;
     if (validate(p, why) != LBM_OK || !bytes) return LBM_EINVAL;
-    *bytes = (size_t)Q * qstride_of(p) * dtype_size(p->dtype);
+    *bytes = (size_t)p->stencil * qstride_of(p) * dtype_size(p->dtype);
     return LBM_OK;
 }
 
@@ -190,26 +195,26 @@ static void set_coll(lbm_ctx *c) {
         wm = 1.0 / (0.5 + p.trt_magic / tau_p);
         kappa = -wm * wm * p.trt_magic / (tau_p * tau_p * wp * wp);
     }
-    Coll<double> d;
+    Coll<double> d = {};
     d.wp = wp;
     d.wm = wm;
     d.kappa = kappa;
     for (int k = 0; k < 3; ++k) d.ah[k] = 0.5 * p.accel[k];
-    for (int pp = 0; pp < 9; ++pp) {
+    for (int pp = 0; pp < (p.stencil - 1) / 2; ++pp) {
         const int q = 2 * pp + 1;
         const double ca = kC[q].x * p.accel[0] + kC[q].y * p.accel[1] + kC[q].z * p.accel[2];
-        d.fraw[pp] = 3.0 * weight(q) * ca;
+        d.fraw[pp] = 3.0 * wq(p.stencil, q) * ca;
         d.fpair[pp] = (1.0 - 0.5 * wm) * d.fraw[pp];
     }
     d.s = c->scale;
     d.inv_s = 1.0 / c->scale;
     d.compressible = p.compressible;
-    Coll<float> f;
+    Coll<float> f = {};
     f.wp = (float)d.wp;
     f.wm = (float)d.wm;
     f.kappa = (float)d.kappa;
     for (int k = 0; k < 3; ++k) f.ah[k] = (float)d.ah[k];
-    for (int pp = 0; pp < 9; ++pp) {
+    for (int pp = 0; pp < 13; ++pp) {
         f.fraw[pp] = (float)d.fraw[pp];
         f.fpair[pp] = (float)d.fpair[pp];
     }
@@ -230,7 +235,7 @@ static void *state_of(const lbm_ctx *c) {
 }
 
 static int totals(lbm_ctx *c, double *rho, double *u, double *sums) {
-    hipError_t e = launch_moments(c->g, c->p.dtype, layout_of(c), 1.0 / c->scale,
+    hipError_t e = launch_moments(c->g, c->p.stencil, c->p.dtype, layout_of(c), 1.0 / c->scale,
                                   c->p.compressible, c->coll.d.ah, state_of(c), rho, u, c->sc,
                                   c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "moments");
@@ -306,7 +311,7 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
             c->scale = p->scale;
         } else {
             double maxdev = 0.0;
-            e = launch_init_maxdev(g, p->equilibrium, p->compressible, rho_init, u_init, c->sc,
+            e = launch_init_maxdev(g, p->stencil, p->equilibrium, p->compressible, rho_init, u_init, c->sc,
                                    c->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(&maxdev, c->sc.result, sizeof(double), hipMemcpyDeviceToHost,
@@ -324,7 +329,7 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
     }
     set_coll(c);
     const Layout lay = p->pattern == LBM_TWO_GRID ? kDirect : kAALocal;
-    e = launch_init(g, p->dtype, p->equilibrium, p->compressible, lay, rho_init, u_init, pdf0,
+    e = launch_init(g, p->stencil, p->dtype, p->equilibrium, p->compressible, lay, rho_init, u_init, pdf0,
                     p->pattern == LBM_TWO_GRID ? pdf1 : nullptr, c->scale, c->stream);
     if (e != hipSuccess) {
         lbm_destroy(c);
@@ -351,13 +356,13 @@ extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
         hipError_t e;
         if (c->p.pattern == LBM_TWO_GRID) {
-            e = launch_step_tg(c->g, c->p.dtype, c->p.equilibrium, c->gen, c->coll,
+            e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->gen, c->coll,
                                c->buf[c->cur], c->buf[1 - c->cur], c->stream);
             if (e == hipSuccess) c->cur ^= 1;
         } else {
             // even step count: the state is in local layout, so the next step
             // is a neighbour step; odd: a local step.
-            e = launch_step_aa(c->g, c->p.dtype, c->p.equilibrium, c->gen, (c->t & 1) == 0,
+            e = launch_step_aa(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->gen, (c->t & 1) == 0,
                                c->coll, c->buf[0], c->stream);
         }
         if (e != hipSuccess) return hip_fail(c, e, "step");
@@ -369,7 +374,7 @@ extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
 extern "C" int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst) {
     if (!c) return LBM_EINVAL;
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct buffers");
-    hipError_t e = launch_step_tg(c->g, c->p.dtype, c->p.equilibrium, c->gen, c->coll, src, dst,
+    hipError_t e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->gen, c->coll, src, dst,
                                   c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "stream_collide");
     return LBM_OK;
@@ -399,7 +404,7 @@ extern "C" int lbm_moments(lbm_ctx *c, double *rho, double *u, double *sums) {
 extern "C" int lbm_get_pdfs(lbm_ctx *c, double *canonical) {
     if (!c) return LBM_EINVAL;
     if (!canonical) return fail(c, LBM_EINVAL, "canonical is NULL");
-    hipError_t e = launch_get(c->g, c->p.dtype, layout_of(c), 1.0 / c->scale, state_of(c),
+    hipError_t e = launch_get(c->g, c->p.stencil, c->p.dtype, layout_of(c), 1.0 / c->scale, state_of(c),
                               canonical, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "get_pdfs");
     return LBM_OK;
@@ -408,7 +413,7 @@ extern "C" int lbm_get_pdfs(lbm_ctx *c, double *canonical) {
 extern "C" int lbm_set_pdfs(lbm_ctx *c, const double *canonical) {
     if (!c) return LBM_EINVAL;
     if (!canonical) return fail(c, LBM_EINVAL, "canonical is NULL");
-    hipError_t e = launch_set(c->g, c->p.dtype, layout_of(c), c->scale, canonical, state_of(c),
+    hipError_t e = launch_set(c->g, c->p.stencil, c->p.dtype, layout_of(c), c->scale, canonical, state_of(c),
                               c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_pdfs");
     return LBM_OK;
@@ -445,6 +450,7 @@ extern "C" int lbm_set_rates(lbm_ctx *c, double omega, const double *accel) {
 extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next,
                                 void *lam_prev, double *grad) {
     if (!c) return LBM_EINVAL;
+    if (c->p.stencil != 19) return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
     if (!state_t || !lam_next || !lam_prev || lam_next == lam_prev)
@@ -457,6 +463,7 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam
 
 extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *out, void *lam) {
     if (!c) return LBM_EINVAL;
+    if (c->p.stencil != 19) return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "objectives are defined for the incompressible form only");
     if (kind != LBM_OBJ_KINETIC_ENERGY && kind != LBM_OBJ_OUTLET_FLUX)
@@ -470,6 +477,7 @@ extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *ou
 
 extern "C" int lbm_init_vjp(lbm_ctx *c, const double *u_init, const void *lam0, double *grad_u) {
     if (!c) return LBM_EINVAL;
+    if (c->p.stencil != 19) return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
     if (!u_init || !lam0 || !grad_u) return fail(c, LBM_EINVAL, "u_init, lam0, grad_u must be set");

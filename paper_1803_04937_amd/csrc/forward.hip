@@ -15,17 +15,18 @@ namespace lbm {
 // ---------------------------------------------------------------------------
 
 // Shifted equilibrium f^eq_q - w_q = w_q [drho + rho0 (E + 3 c_q.u)] of all
-// 19 directions, in FP64.
-template <int EQ>
+// QN directions, in FP64.
+template <int EQ, int QN>
 __device__ __forceinline__ void shifted_feq(double drho, double rho0, double ux, double uy,
-                                            double uz, double (&d)[Q]) {
-    double cu[9], E[9], E0;
-    Poly::even<double, EQ>(ux, uy, uz, cu, E, E0);
-    d[0] = weight(0) * (drho + rho0 * E0);
+                                            double uz, double (&d)[QN]) {
+    constexpr int NP = (QN - 1) / 2;
+    double cu[NP], E[NP], E0;
+    Poly::even<double, EQ, NP>(ux, uy, uz, cu, E, E0);
+    d[0] = wq(QN, 0) * (drho + rho0 * E0);
 #pragma unroll
-    for (int p = 0; p < 9; ++p) {
+    for (int p = 0; p < NP; ++p) {
         const int q = 2 * p + 1;
-        const double w = weight(q);
+        const double w = wq(QN, q);
         d[q] = w * (drho + rho0 * (E[p] + 3.0 * cu[p]));
         d[q + 1] = w * (drho + rho0 * (E[p] - 3.0 * cu[p]));
     }
@@ -60,7 +61,7 @@ __device__ __forceinline__ bool is_solid(const Geom &g, uint32_t idx) {
 // Initial state f = f^eq(rho, u) (no force shift); solid cells f = w.
 // Written into A (in the given layout) and, if B != null, into B as well.
 // ---------------------------------------------------------------------------
-template <int DT, int EQ>
+template <int QN, int DT, int EQ>
 __global__ __launch_bounds__(kBlock) void k_init(Geom g, int compressible, Layout layout,
                                                  const double *__restrict__ rho,
                                                  const double *__restrict__ u,
@@ -70,29 +71,29 @@ __global__ __launch_bounds__(kBlock) void k_init(Geom g, int compressible, Layou
     using R = typename S::R;
     const uint32_t idx = cell_index();
     if (idx >= g.ncells) return;
-    double d[Q];
+    double d[QN];
     if (is_solid(g, idx)) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) d[q] = 0.0;
+        for (int q = 0; q < QN; ++q) d[q] = 0.0;
     } else {  // shifted equilibrium; written below as w + d (raw) or d (shifted)
         const double r = rho ? rho[idx] : 1.0;
         const double rho0 = compressible ? r : 1.0;
-        shifted_feq<EQ>(r - 1.0, rho0, u[idx], u[g.ncells + idx], u[2 * (size_t)g.ncells + idx],
+        shifted_feq<EQ, QN>(r - 1.0, rho0, u[idx], u[g.ncells + idx], u[2 * (size_t)g.ncells + idx],
                         d);
     }
     const Hood h = make_hood(idx, g);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < QN; ++q) {
         int arr;
         uint32_t cell;
         canonical_slot<true>(h, g, layout, q, arr, cell);
-        S::store(A + arr * g.qstride, cell, (R)d[q], (R)weight(q), (R)s);
-        if (B) S::store(B + arr * g.qstride, cell, (R)d[q], (R)weight(q), (R)s);
+        S::store(A + arr * g.qstride, cell, (R)d[q], (R)wq(QN, q), (R)s);
+        if (B) S::store(B + arr * g.qstride, cell, (R)d[q], (R)wq(QN, q), (R)s);
     }
 }
 
 // max over fluid cells and q of |f^eq_q - w_q| of the initial state.
-template <int EQ>
+template <int QN, int EQ>
 __global__ __launch_bounds__(kBlock) void k_init_maxdev(Geom g, int compressible,
                                                         const double *__restrict__ rho,
                                                         const double *__restrict__ u,
@@ -101,11 +102,11 @@ __global__ __launch_bounds__(kBlock) void k_init_maxdev(Geom g, int compressible
     double m[1] = {0.0};
     if (idx < g.ncells && !is_solid(g, idx)) {
         const double r = rho ? rho[idx] : 1.0;
-        double d[Q];
-        shifted_feq<EQ>(r - 1.0, compressible ? r : 1.0, u[idx], u[g.ncells + idx],
+        double d[QN];
+        shifted_feq<EQ, QN>(r - 1.0, compressible ? r : 1.0, u[idx], u[g.ncells + idx],
                         u[2 * (size_t)g.ncells + idx], d);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) m[0] = fmax(m[0], fabs(d[q]));
+        for (int q = 0; q < QN; ++q) m[0] = fmax(m[0], fabs(d[q]));
     }
     block_reduce<1, true>(m, partials + blockIdx.x);
 }
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_init_maxdev(Geom g, int compressible
 // ---------------------------------------------------------------------------
 // Two-grid pull step: dst[q][x] = f*_q(x) from src.
 // ---------------------------------------------------------------------------
-template <int DT, int EQ, bool GEN>
+template <int QN, int DT, int EQ, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<DT>::R> P,
                                                     const typename Store<DT>::T *__restrict__ src,
                                                     typename Store<DT>::T *__restrict__ dst) {
@@ -123,17 +124,17 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
     if (idx >= g.ncells) return;
     if (GEN && is_solid(g, idx)) return;
     const Hood h = make_hood(idx, g);
-    R d[Q];
+    R d[QN];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < QN; ++q) {
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
         const typename S::T *p = src + (fl ? q : opp(q)) * g.qstride;
-        d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s, nt_load_fwd(kC[q].x));
+        d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_fwd(kC[q].x));
     }
-    collide<R, EQ>(d, P);
+    collide<R, EQ, QN>(d, P);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) S::store(dst + q * g.qstride, idx, d[q], (R)weight(q), P.s);
+    for (int q = 0; q < QN; ++q) S::store(dst + q * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
 }
 
 // ---------------------------------------------------------------------------
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
 // Every slot a cell reads is written by the same cell, so the in-place
 // update is race-free.
 // ---------------------------------------------------------------------------
-template <int DT, int EQ, bool GEN>
+template <int QN, int DT, int EQ, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Store<DT>::R> P,
                                                        typename Store<DT>::T *A) {
     using S = Store<DT>;
@@ -154,25 +155,25 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
     if (idx >= g.ncells) return;
     if (GEN && is_solid(g, idx)) return;
     const Hood h = make_hood(idx, g);
-    R d[Q];
+    R d[QN];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < QN; ++q) {
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
         const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
-        d[q] = S::load(p, fl ? c : idx, (R)weight(q), P.inv_s, nt_load_fwd(kC[q].x));
+        d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_fwd(kC[q].x));
     }
-    collide<R, EQ>(d, P);
+    collide<R, EQ, QN>(d, P);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < QN; ++q) {
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, +1, fl);
         typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
-        S::store(p, fl ? c : idx, d[q], (R)weight(q), P.s, nt_store(kC[q].x));
+        S::store(p, fl ? c : idx, d[q], (R)wq(QN, q), P.s, nt_store(kC[q].x));
     }
 }
 
-template <int DT, int EQ, bool GEN>
+template <int QN, int DT, int EQ, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename Store<DT>::R> P,
                                                         typename Store<DT>::T *A) {
     using S = Store<DT>;
@@ -180,19 +181,19 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename St
     const uint32_t idx = cell_index();
     if (idx >= g.ncells) return;
     if (GEN && is_solid(g, idx)) return;
-    R d[Q];
+    R d[QN];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) d[q] = S::load(A + q * g.qstride, idx, (R)weight(q), P.inv_s);
-    collide<R, EQ>(d, P);
+    for (int q = 0; q < QN; ++q) d[q] = S::load(A + q * g.qstride, idx, (R)wq(QN, q), P.inv_s);
+    collide<R, EQ, QN>(d, P);
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-        S::store(A + opp(q) * g.qstride, idx, d[q], (R)weight(q), P.s);
+    for (int q = 0; q < QN; ++q)
+        S::store(A + opp(q) * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
 }
 
 // ---------------------------------------------------------------------------
-// Canonical read-out / write-in (FP64 dense [19][cells]).
+// Canonical read-out / write-in (FP64 dense [QN][cells]).
 // ---------------------------------------------------------------------------
-template <int DT>
+template <int QN, int DT>
 __global__ __launch_bounds__(kBlock) void k_get(Geom g, Layout layout, double inv_s,
                                                 const typename Store<DT>::T *__restrict__ A,
                                                 double *__restrict__ out) {
@@ -203,19 +204,19 @@ __global__ __launch_bounds__(kBlock) void k_get(Geom g, Layout layout, double in
     const bool solid = is_solid(g, idx);
     const Hood h = make_hood(idx, g);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        double v = weight(q);
+    for (int q = 0; q < QN; ++q) {
+        double v = wq(QN, q);
         if (!solid) {
             int arr;
             uint32_t cell;
             canonical_slot<true>(h, g, layout, q, arr, cell);
-            v = load_canonical<DT>(A + arr * g.qstride, cell, weight(q), inv_s);
+            v = load_canonical<DT>(A + arr * g.qstride, cell, wq(QN, q), inv_s);
         }
         out[(size_t)q * g.ncells + idx] = v;
     }
 }
 
-template <int DT>
+template <int QN, int DT>
 __global__ __launch_bounds__(kBlock) void k_set(Geom g, Layout layout, double s,
                                                 const double *__restrict__ in,
                                                 typename Store<DT>::T *A) {
@@ -226,22 +227,22 @@ __global__ __launch_bounds__(kBlock) void k_set(Geom g, Layout layout, double s,
     const bool solid = is_solid(g, idx);
     const Hood h = make_hood(idx, g);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < QN; ++q) {
         if (solid) {
-            S::store(A + q * g.qstride, idx, (R)0, (R)weight(q), (R)s);
+            S::store(A + q * g.qstride, idx, (R)0, (R)wq(QN, q), (R)s);
         } else {
             int arr;
             uint32_t cell;
             canonical_slot<true>(h, g, layout, q, arr, cell);
             store_canonical<DT>(A + arr * g.qstride, cell, in[(size_t)q * g.ncells + idx],
-                                weight(q), s);
+                                wq(QN, q), s);
         }
     }
 }
 
 // rho = sum f*, u = (sum c f* - a/2) / rho0' per cell (FP64), and block
 // partials of the FP64 totals of rho and sum c f* over fluid cells.
-template <int DT>
+template <int QN, int DT>
 __global__ __launch_bounds__(kBlock) void k_moments(Geom g, Layout layout, double inv_s,
                                                     int compressible, double ahx, double ahy,
                                                     double ahz,
@@ -256,16 +257,16 @@ __global__ __launch_bounds__(kBlock) void k_moments(Geom g, Layout layout, doubl
         double r = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
         if (!is_solid(g, idx)) {
             const Hood h = make_hood(idx, g);
-            double d[Q];
+            double d[QN];
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
+            for (int q = 0; q < QN; ++q) {
                 int arr;
                 uint32_t cell;
                 canonical_slot<true>(h, g, layout, q, arr, cell);
-                d[q] = (double)S::load(A + arr * g.qstride, cell, (R)weight(q), (R)inv_s);
+                d[q] = (double)S::load(A + arr * g.qstride, cell, (R)wq(QN, q), (R)inv_s);
             }
             double drho, jx, jy, jz;
-            moments<double>(d, drho, jx, jy, jz);
+            moments<double, QN>(d, drho, jx, jy, jz);
             r = 1.0 + drho;
             tot[0] = r;
             tot[1] = jx;
@@ -373,31 +374,37 @@ const Coll<float> &pick<LBM_BF16_SHIFTED>(const CollBoth &P) { return P.f; }
     default: return hipErrorInvalidValue;                             \
     }
 
-#define LBM_DISPATCH_EQ(eq, BODY)                                        \
-    if (eq == LBM_EQ_IMPROVED) { constexpr int EQ = LBM_EQ_IMPROVED; BODY; } \
-    else { constexpr int EQ = LBM_EQ_STANDARD; BODY; }
+// D3Q27 has one equilibrium (the standard form, Sec. 3.1).
+#define LBM_DISPATCH_EQ(eq, BODY)                                                              \
+    if (qn == 27) { constexpr int QN = 27; constexpr int EQ = LBM_EQ_STANDARD; BODY; }         \
+    else if (eq == LBM_EQ_IMPROVED) { constexpr int QN = 19; constexpr int EQ = LBM_EQ_IMPROVED; BODY; } \
+    else { constexpr int QN = 19; constexpr int EQ = LBM_EQ_STANDARD; BODY; }
+
+#define LBM_DISPATCH_Q(BODY)                              \
+    if (qn == 27) { constexpr int QN = 27; BODY; }        \
+    else { constexpr int QN = 19; BODY; }
 
 #define LBM_DISPATCH_GEN(gen, BODY)                      \
     if (gen) { constexpr bool GEN = true; BODY; }        \
     else { constexpr bool GEN = false; BODY; }
 
-hipError_t launch_init(const Geom &g, int dtype, int eq, int compressible, Layout layout,
+hipError_t launch_init(const Geom &g, int qn, int dtype, int eq, int compressible, Layout layout,
                        const double *rho, const double *u, void *A, void *B, double s,
                        hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, {
         using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_init<DT, EQ>), grid, block, 0, st, g, compressible, layout, rho, u,
+        hipLaunchKernelGGL((k_init<QN, DT, EQ>), grid, block, 0, st, g, compressible, layout, rho, u,
                            (T *)A, (T *)B, s);
     }));
     return hipGetLastError();
 }
 
-hipError_t launch_init_maxdev(const Geom &g, int eq, int compressible, const double *rho,
+hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, const double *rho,
                               const double *u, const Scratch &sc, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
     LBM_DISPATCH_EQ(eq, {
-        hipLaunchKernelGGL((k_init_maxdev<EQ>), grid, block, 0, st, g, compressible, rho, u,
+        hipLaunchKernelGGL((k_init_maxdev<QN, EQ>), grid, block, 0, st, g, compressible, rho, u,
                            sc.partials);
     });
     hipError_t e = hipGetLastError();
@@ -405,61 +412,62 @@ hipError_t launch_init_maxdev(const Geom &g, int eq, int compressible, const dou
     return launch_finalize(sc, cell_blocks(g), 1, 1, sc.result, false, st);
 }
 
-hipError_t launch_step_tg(const Geom &g, int dtype, int eq, bool gen, const CollBoth &P,
+hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool gen, const CollBoth &P,
                           const void *src, void *dst, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, {
         using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_step_tg<DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
+        hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
                            (const T *)src, (T *)dst);
     })));
     return hipGetLastError();
 }
 
-hipError_t launch_step_aa(const Geom &g, int dtype, int eq, bool gen, bool neighbor,
+hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool gen, bool neighbor,
                           const CollBoth &P, void *A, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, {
         using T = typename Store<DT>::T;
         if (neighbor)
-            hipLaunchKernelGGL((k_step_aa_nb<DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
+            hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
                                (T *)A);
         else
-            hipLaunchKernelGGL((k_step_aa_loc<DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
+            hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
                                (T *)A);
     })));
     return hipGetLastError();
 }
 
-hipError_t launch_get(const Geom &g, int dtype, Layout layout, double inv_s, const void *A,
+hipError_t launch_get(const Geom &g, int qn, int dtype, Layout layout, double inv_s, const void *A,
                       double *out, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, {
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_Q({
         using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_get<DT>), grid, block, 0, st, g, layout, inv_s, (const T *)A, out);
-    });
+        hipLaunchKernelGGL((k_get<QN, DT>), grid, block, 0, st, g, layout, inv_s, (const T *)A,
+                           out);
+    }));
     return hipGetLastError();
 }
 
-hipError_t launch_set(const Geom &g, int dtype, Layout layout, double s, const double *in,
+hipError_t launch_set(const Geom &g, int qn, int dtype, Layout layout, double s, const double *in,
                       void *A, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, {
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_Q({
         using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_set<DT>), grid, block, 0, st, g, layout, s, in, (T *)A);
-    });
+        hipLaunchKernelGGL((k_set<QN, DT>), grid, block, 0, st, g, layout, s, in, (T *)A);
+    }));
     return hipGetLastError();
 }
 
-hipError_t launch_moments(const Geom &g, int dtype, Layout layout, double inv_s,
+hipError_t launch_moments(const Geom &g, int qn, int dtype, Layout layout, double inv_s,
                           int compressible, const double ah[3], const void *A, double *rho,
                           double *u, const Scratch &sc, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, {
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_Q({
         using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_moments<DT>), grid, block, 0, st, g, layout, inv_s, compressible,
-                           ah[0], ah[1], ah[2], (const T *)A, rho, u, sc.partials);
-    });
+        hipLaunchKernelGGL((k_moments<QN, DT>), grid, block, 0, st, g, layout, inv_s,
+                           compressible, ah[0], ah[1], ah[2], (const T *)A, rho, u, sc.partials);
+    }));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(sc, cell_blocks(g), 4, 0, sc.result, false, st);

@@ -1,5 +1,6 @@
 // Host-side launch interface between the C ABI (api.hip) and the kernel
-// translation units (forward.hip, adjoint.hip).
+// translation units (forward.hip, adjoint.hip).  qn is the stencil size (19
+// or 27); the adjoint launchers are D3Q19 only.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,20 +35,20 @@ struct Scratch {
 
 constexpr uint32_t kReduceChunk = 1024;  // partials folded per block and pass
 
-hipError_t launch_init(const Geom &g, int dtype, int eq, int compressible, Layout layout,
+hipError_t launch_init(const Geom &g, int qn, int dtype, int eq, int compressible, Layout layout,
                        const double *rho, const double *u, void *A, void *B, double s,
                        hipStream_t st);
-hipError_t launch_init_maxdev(const Geom &g, int eq, int compressible, const double *rho,
+hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, const double *rho,
                               const double *u, const Scratch &sc, hipStream_t st);
-hipError_t launch_step_tg(const Geom &g, int dtype, int eq, bool gen, const CollBoth &P,
+hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool gen, const CollBoth &P,
                           const void *src, void *dst, hipStream_t st);
-hipError_t launch_step_aa(const Geom &g, int dtype, int eq, bool gen, bool neighbor,
+hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool gen, bool neighbor,
                           const CollBoth &P, void *A, hipStream_t st);
-hipError_t launch_get(const Geom &g, int dtype, Layout layout, double inv_s, const void *A,
+hipError_t launch_get(const Geom &g, int qn, int dtype, Layout layout, double inv_s, const void *A,
                       double *out, hipStream_t st);
-hipError_t launch_set(const Geom &g, int dtype, Layout layout, double s, const double *in,
+hipError_t launch_set(const Geom &g, int qn, int dtype, Layout layout, double s, const double *in,
                       void *A, hipStream_t st);
-hipError_t launch_moments(const Geom &g, int dtype, Layout layout, double inv_s,
+hipError_t launch_moments(const Geom &g, int qn, int dtype, Layout layout, double inv_s,
                           int compressible, const double ah[3], const void *A, double *rho,
                           double *u, const Scratch &sc, hipStream_t st);
 hipError_t launch_adjoint(const Geom &g, int dtype, int ltype, int eq, bool gen,

@@ -1,6 +1,8 @@
-// Device-side building blocks of the D3Q19 stream-collide library (gfx950).
+// Device-side building blocks of the D3Q19 / D3Q27 stream-collide library
+// (gfx950).
 //
-// Lattice: D3Q19 (Sec. 2.3), direction order fixed by include/lbm.h.
+// Lattices: D3Q19 and D3Q27 (Sec. 2.3), direction order fixed by
+// include/lbm.h (D3Q27 = the 19 D3Q19 directions followed by the 8 corners).
 // Arithmetic is done in "shifted" variables d_q = f_q - w_q: moments,
 // equilibrium and collision are written in d, which keeps FP32 accurate for
 // the small deviations of f from the rest state and lets the 16-bit storage
@@ -14,23 +16,34 @@
 
 namespace lbm {
 
-constexpr int Q = 19;
-constexpr int kBlock = 256;  // threads per block for every cell kernel
+constexpr int Q = 19;         // D3Q19 (the adjoint is written for it)
+constexpr int kQMax = 27;     // D3Q27
+constexpr int kBlock = 256;   // threads per block for every cell kernel
 
 // ---------------------------------------------------------------------------
-// Velocity set (Sec. 2.3).  Opposite pairs are (2k-1, 2k), k = 1..9.
+// Velocity sets (Sec. 2.3).  Opposite pairs are (2k-1, 2k), k = 1..9 for
+// D3Q19 and k = 1..13 for D3Q27.
 // ---------------------------------------------------------------------------
 struct Vec3i {
     int x, y, z;
 };
-constexpr Vec3i kC[Q] = {
+constexpr Vec3i kC[kQMax] = {
     {0, 0, 0},  {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
     {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1},
     {-1, 0, 1}, {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1},
+    {1, -1, -1},
 };
 __host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+// D3Q19 weights: 1/3, 1/18, 1/36.
 __host__ __device__ constexpr double weight(int q) {
     return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+// Weights of the QN-direction stencil; D3Q27: 8/27, 2/27, 1/54, 1/216.
+__host__ __device__ constexpr double wq(int qn, int q) {
+    return qn == 19 ? weight(q)
+                    : (q == 0 ? 8.0 / 27.0
+                              : (q <= 6 ? 2.0 / 27.0 : (q <= 18 ? 1.0 / 54.0 : 1.0 / 216.0)));
 }
 
 // ---------------------------------------------------------------------------
@@ -273,16 +286,16 @@ template <typename R>
 struct Coll {
     R wp, wm;       // even / odd relaxation rates (equal for SRT)
     R ah[3];        // a / 2
-    R fpair[9];     // (1 - wm/2) * 3 w_p (c_p . a) for the pair of q = 2p + 1
-    R fraw[9];      // 3 w_p (c_p . a)
+    R fpair[13];    // (1 - wm/2) * 3 w_p (c_p . a) for the pair of q = 2p + 1
+    R fraw[13];     // 3 w_p (c_p . a)
     R kappa;        // d omega_minus / d omega (1 for SRT)
     R s, inv_s;     // storage scale
     int compressible;
 };
 
 // Moments of shifted PDFs: drho = sum d, j = sum c d.
-template <typename R>
-__device__ __forceinline__ void moments(const R (&d)[Q], R &drho, R &jx, R &jy, R &jz) {
+template <typename R, int QN = 19>
+__device__ __forceinline__ void moments(const R (&d)[QN], R &drho, R &jx, R &jy, R &jz) {
     const R p1 = d[1] - d[2], p3 = d[3] - d[4], p5 = d[5] - d[6], p7 = d[7] - d[8],
             p9 = d[9] - d[10], p11 = d[11] - d[12], p13 = d[13] - d[14], p15 = d[15] - d[16],
             p17 = d[17] - d[18];
@@ -292,6 +305,15 @@ __device__ __forceinline__ void moments(const R (&d)[Q], R &drho, R &jx, R &jy, 
     drho = ((d[0] + (d[1] + d[2])) + ((d[3] + d[4]) + (d[5] + d[6]))) +
            (((d[7] + d[8]) + (d[9] + d[10])) + ((d[11] + d[12]) + (d[13] + d[14]))) +
            ((d[15] + d[16]) + (d[17] + d[18]));
+    if constexpr (QN == 27) {
+        // corners (1,1,1), (1,1,-1), (1,-1,1), (-1,1,1) and their opposites
+        const R p19 = d[19] - d[20], p21 = d[21] - d[22], p23 = d[23] - d[24],
+                p25 = d[25] - d[26];
+        jx += (p19 + p21) + (p23 - p25);
+        jy += (p19 + p21) + (p25 - p23);
+        jz += (p19 - p21) + (p23 + p25);
+        drho += ((d[19] + d[20]) + (d[21] + d[22])) + ((d[23] + d[24]) + (d[25] + d[26]));
+    }
 }
 
 // Even part E_p of the equilibrium polynomial for the pair of q = 2p + 1
@@ -299,8 +321,10 @@ __device__ __forceinline__ void moments(const R (&d)[Q], R &drho, R &jx, R &jy, 
 // E = 9/2 (c.u)^2 - 3/2 u^2.  Improved (eq. new_d3q19_equilibrium): axis
 // 6 u_a^2 - 3 u^2, edge 9/2 (c.u)^2 - 3/2 (u_a^2 + u_b^2), rest -u^2.
 struct Poly {
-    template <typename R, int EQ>
-    static __device__ __forceinline__ void even(R ux, R uy, R uz, R (&cu)[9], R (&E)[9], R &E0) {
+    // NP = (QN - 1) / 2 pairs; D3Q27 has the standard form only (Sec. 3.1:
+    // moment matching on D3Q27 gives it).
+    template <typename R, int EQ, int NP = 9>
+    static __device__ __forceinline__ void even(R ux, R uy, R uz, R (&cu)[NP], R (&E)[NP], R &E0) {
         const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz, uu = ux2 + uy2 + uz2;
         cu[0] = ux;
         cu[1] = uy;
@@ -311,7 +335,13 @@ struct Poly {
         cu[6] = ux - uz;
         cu[7] = uy + uz;
         cu[8] = uy - uz;
-        if (EQ == LBM_EQ_IMPROVED) {
+        if constexpr (NP == 13) {
+            cu[9] = (ux + uy) + uz;
+            cu[10] = (ux + uy) - uz;
+            cu[11] = (ux - uy) + uz;
+            cu[12] = (uy - ux) + uz;
+        }
+        if (EQ == LBM_EQ_IMPROVED && NP == 9) {
             E0 = -uu;
             E[0] = R(6) * ux2 - R(3) * uu;
             E[1] = R(6) * uy2 - R(3) * uu;
@@ -328,30 +358,31 @@ struct Poly {
             const R t = R(1.5) * uu;
             E0 = -t;
 #pragma unroll
-            for (int p = 0; p < 9; ++p) E[p] = R(4.5) * cu[p] * cu[p] - t;
+            for (int p = 0; p < NP; ++p) E[p] = R(4.5) * cu[p] * cu[p] - t;
         }
     }
 };
 
 // Stream-collide of one cell in shifted variables, in place on d.
-template <typename R, int EQ>
-__device__ __forceinline__ void collide(R (&d)[Q], const Coll<R> &P) {
+template <typename R, int EQ, int QN = 19>
+__device__ __forceinline__ void collide(R (&d)[QN], const Coll<R> &P) {
+    constexpr int NP = (QN - 1) / 2;
     R drho, jx, jy, jz;
-    moments(d, drho, jx, jy, jz);
+    moments<R, QN>(d, drho, jx, jy, jz);
     R rho0 = R(1), inv = R(1);
     if (P.compressible) {
         rho0 = R(1) + drho;
         inv = R(1) / rho0;
     }
     const R ux = (jx + P.ah[0]) * inv, uy = (jy + P.ah[1]) * inv, uz = (jz + P.ah[2]) * inv;
-    R cu[9], E[9], E0;
-    Poly::even<R, EQ>(ux, uy, uz, cu, E, E0);
-    const R w0 = R(1.0 / 3.0);
+    R cu[NP], E[NP], E0;
+    Poly::even<R, EQ, NP>(ux, uy, uz, cu, E, E0);
+    const R w0 = R(wq(QN, 0));
     d[0] = d[0] - P.wp * (d[0] - w0 * (drho + rho0 * E0));
 #pragma unroll
-    for (int p = 0; p < 9; ++p) {
+    for (int p = 0; p < NP; ++p) {
         const int q = 2 * p + 1;
-        const R w = R(weight(q));
+        const R w = R(wq(QN, q));
         const R np = R(0.5) * (d[q] + d[q + 1]) - w * (drho + rho0 * E[p]);
         const R nm = R(0.5) * (d[q] - d[q + 1]) - w * rho0 * (R(3) * cu[p]);
         const R tp = P.wp * np;

@@ -38,9 +38,11 @@ K_CENTRE = _square_duct_centre_constant()
 
 
 def duct_spurious_current(D: int, lam2: float, equilibrium: str, dtype: str = "f64",
-                          re: float = 10.0, sweeps: float = 3.0, device=None) -> dict:
+                          re: float = 10.0, sweeps: float = 3.0, stencil: int = 19,
+                          device=None) -> dict:
     """Steady-state max |u_y| / max u_x of the duct for one resolution D,
-    one Lambda^2 and one equilibrium ("standard" or "improved")."""
+    one Lambda^2 and one equilibrium ("standard" or "improved"; D3Q27 has a
+    single equilibrium)."""
     import lbm_inputs
     lam = math.sqrt(lam2)
     omega = 1.0 / (lam + 0.5)
@@ -48,7 +50,8 @@ def duct_spurious_current(D: int, lam2: float, equilibrium: str, dtype: str = "f
     a = re * nu * nu / (K_CENTRE * (D / 2.0) ** 2 * D)
     u0 = torch.as_tensor(lbm_inputs.duct_poiseuille(1, D, D, a, nu))
     lat = Lattice(1, D, D, u=u0, periodic=(1, 0, 0), equilibrium=equilibrium, collision="srt",
-                  dtype=dtype, omega=omega, accel=(a, 0.0, 0.0), device=device)
+                  dtype=dtype, omega=omega, accel=(a, 0.0, 0.0), stencil=stencil,
+                  device=device)
     steps = int(math.ceil(sweeps * D * D / nu))
     chunks = 10
     per = max(1, steps // chunks)
@@ -61,7 +64,8 @@ def duct_spurious_current(D: int, lam2: float, equilibrium: str, dtype: str = "f
         history.append(uy / ux)
     lat.close()
     last, prev = history[-1], history[-2]
-    return {"D": D, "lambda2": lam2, "omega": omega, "equilibrium": equilibrium, "dtype": dtype,
+    return {"D": D, "lambda2": lam2, "omega": omega, "stencil": stencil,
+            "equilibrium": equilibrium if stencil == 19 else "d3q27", "dtype": dtype,
             "steps": per * chunks, "ratio": last, "ux_max": ux,
             "last_chunk_rel_change": abs(last - prev) / max(abs(last), 1e-300)}
 
@@ -80,6 +84,7 @@ def main():
     ap.add_argument("--dtype", default="f64")
     ap.add_argument("--sizes", default="15,25,35,45,65")
     ap.add_argument("--lambda2", default="0.16,0.0833333333333333")
+    ap.add_argument("--d3q27", action="store_true", help="also run the D3Q27 stencil")
     ap.add_argument("--sweep", type=int, default=0,
                     help="also sweep Lambda^2 at this D for the standard equilibrium")
     a = ap.parse_args()
@@ -93,6 +98,10 @@ def main():
             if eq == "standard":
                 out[key]["order"] = convergence_order(rows)
             print(json.dumps({key: out[key]}), flush=True)
+    if a.d3q27:
+        for lam2 in [float(v) for v in a.lambda2.split(",")]:
+            rows = [duct_spurious_current(D, lam2, "standard", a.dtype, stencil=27) for D in sizes]
+            print(json.dumps({f"d3q27_lambda2={lam2:.4f}": {"rows": rows}}), flush=True)
     if a.sweep:
         lams = [0.01, 0.02, 0.04, 0.06, 1.0 / 12.0, 0.1, 0.12, 0.16, 0.25]
         sweep = [(l2, duct_spurious_current(a.sweep, l2, "standard", a.dtype)["ratio"])

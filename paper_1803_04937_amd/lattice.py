@@ -32,7 +32,8 @@ def require_gpu(device=None):
 
 
 class Lattice:
-    """A D3Q19 lattice (shape nz x ny x nx, x fastest) with its PDF buffers.
+    """A D3Q19 or D3Q27 lattice (shape nz x ny x nx, x fastest) with its PDF
+    buffers.
 
     u: initial velocity, tensor (3, nz, ny, nx); rho: optional density
     (nz, ny, nx); solid: optional mask (nz, ny, nx), nonzero = solid.
@@ -41,17 +42,18 @@ class Lattice:
     def __init__(self, nx, ny, nz, *, u, rho=None, solid=None, periodic=(1, 1, 1),
                  equilibrium="improved", collision="srt", dtype="f32", pattern="two_grid",
                  compressible=False, omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0),
-                 scale=0.0, device=None, stream=None):
+                 scale=0.0, stencil=19, device=None, stream=None):
         self.device = require_gpu(device)
         self.params = capi.make_params(
             nx, ny, nz, periodic=periodic, equilibrium=_code(EQUILIBRIA, equilibrium),
             collision=_code(COLLISIONS, collision), dtype=_code(DTYPES, dtype),
             pattern=_code(PATTERNS, pattern), compressible=int(bool(compressible)), omega=omega,
-            trt_magic=trt_magic, accel=accel, scale=scale)
+            trt_magic=trt_magic, accel=accel, scale=scale, stencil=stencil)
         rc, why = capi.lbm_validate(self.params)
         if rc != capi.LBM_OK:
             raise LBMError(rc, why)
         self.shape = (int(nz), int(ny), int(nx))
+        self.q = int(stencil)
         self.ncells = int(nx) * int(ny) * int(nz)
         self.qstride = capi.lbm_qstride(self.params)
         self.storage_dtype = STORAGE_TORCH[self.params.dtype]
@@ -76,8 +78,8 @@ class Lattice:
 
     # -- buffers -------------------------------------------------------------
     def new_state(self) -> torch.Tensor:
-        """A state buffer of this lattice's layout: tensor (19, qstride)."""
-        return torch.empty((19, self.qstride), dtype=self.storage_dtype, device=self.device)
+        """A state buffer of this lattice's layout: tensor (Q, qstride)."""
+        return torch.empty((self.q, self.qstride), dtype=self.storage_dtype, device=self.device)
 
     def new_adjoint(self, zero: bool = True) -> torch.Tensor:
         """An adjoint field: tensor (19, qstride) of the adjoint dtype."""
@@ -85,8 +87,8 @@ class Lattice:
         return f((19, self.qstride), dtype=self.adjoint_dtype, device=self.device)
 
     def state_view(self, buf: torch.Tensor) -> torch.Tensor:
-        """(19, nz, ny, nx) view of the cells of a state or adjoint buffer."""
-        return buf[:, :self.ncells].view((19,) + self.shape)
+        """(Q, nz, ny, nx) view of the cells of a state or adjoint buffer."""
+        return buf[:, :self.ncells].view((buf.shape[0],) + self.shape)
 
     @property
     def ctx(self):
@@ -133,13 +135,13 @@ class Lattice:
         return capi.lbm_moments(self.ctx, None, None, want_sums=True)
 
     def get_pdfs(self) -> torch.Tensor:
-        out = torch.empty((19,) + self.shape, dtype=torch.float64, device=self.device)
+        out = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
         capi.lbm_get_pdfs(self.ctx, out)
         return out
 
     def set_pdfs(self, f) -> None:
         f = torch.as_tensor(f).to(self.device, torch.float64).contiguous()
-        assert f.shape == (19,) + self.shape
+        assert f.shape == (self.q,) + self.shape
         capi.lbm_set_pdfs(self.ctx, f)
 
     def watchdog(self, rel_tol: float = 1e-6) -> None:

@@ -19,6 +19,11 @@ import torch
 import oracle
 
 C, W, OPP = oracle.velocity_set()
+W27 = oracle.velocity_set(27)[1]
+
+
+def weights_for(nq):
+    return W27 if nq == 27 else W
 
 DTYPE_NAMES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3, "bf16s": 4}
 
@@ -33,14 +38,14 @@ def host(t):
 
 
 def case(nx, ny, nz, periodic=(1, 1, 1), improved=True, trt=False, omega=1.2, magic=3 / 16,
-         accel=(0.0, 0.0, 0.0), solid=None, compressible=False):
+         accel=(0.0, 0.0, 0.0), solid=None, compressible=False, stencil=19):
     """(oracle.Config, Lattice keyword arguments) of one case."""
     cfg = oracle.Config(nx, ny, nz, periodic=tuple(periodic), improved=improved, trt=trt,
                         compressible=compressible, omega=omega, magic=magic, accel=tuple(accel),
-                        solid=solid)
+                        solid=solid, stencil=stencil)
     kw = dict(periodic=tuple(periodic), equilibrium="improved" if improved else "standard",
               collision="trt" if trt else "srt", compressible=compressible, omega=omega,
-              trt_magic=magic, accel=tuple(accel))
+              trt_magic=magic, accel=tuple(accel), stencil=stencil)
     if solid is not None:
         kw["solid"] = dev(solid, torch.uint8)
     return cfg, kw
@@ -65,7 +70,8 @@ def random_blobs(shape, seed, frac=0.08):
 
 
 def assert_f64_parity(f_gpu, f_ref, what=""):
-    bound = 1e-12 * np.maximum(np.abs(f_ref), W.reshape((19,) + (1,) * (f_ref.ndim - 1)))
+    nq = f_ref.shape[0]
+    bound = 1e-12 * np.maximum(np.abs(f_ref), weights_for(nq).reshape((nq,) + (1,) * (f_ref.ndim - 1)))
     err = np.abs(f_gpu - f_ref)
     worst = np.max(err / bound)
     assert worst <= 1.0, f"{what}: max error {err.max():.3e}, {worst:.2f} x bound"
@@ -86,7 +92,8 @@ def ulp_half(x, dtype):
 
 def reduced_bound(f_ref, dtype, scale):
     """Per-value error bound of one reduced-precision step (see module doc)."""
-    wq = W.reshape((19,) + (1,) * (f_ref.ndim - 1))
+    nq = f_ref.shape[0]
+    wq = weights_for(nq).reshape((nq,) + (1,) * (f_ref.ndim - 1))
     d = f_ref - wq
     arith = 2.0 ** -18 * np.maximum(np.abs(d), wq / 8)
     if dtype == "f32":

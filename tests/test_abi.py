@@ -33,10 +33,11 @@ def test_every_declared_symbol_is_exported(capi):
     assert sorted(capi.EXPORTS) == names
 
 
-def test_velocity_set_matches_oracle(capi):
+@pytest.mark.parametrize("stencil", [19, 27])
+def test_velocity_set_matches_oracle(capi, stencil):
     import oracle
-    c, w, o = capi.lbm_velocity_set()
-    oc, ow, oo = oracle.velocity_set()
+    c, w, o = capi.lbm_velocity_set(stencil)
+    oc, ow, oo = oracle.velocity_set(stencil)
     np.testing.assert_array_equal(np.array(c), oc)
     np.testing.assert_array_equal(np.array(w), ow)
     np.testing.assert_array_equal(np.array(o), oo)
@@ -56,6 +57,8 @@ def test_layout_sizes(capi):
     assert capi.lbm_state_bytes(p16) == 19 * capi.lbm_qstride(p16) * 2
     p64 = capi.make_params(7, 5, 3, dtype=capi.LBM_F64)
     assert capi.lbm_state_bytes(p64) == 19 * capi.lbm_qstride(p64) * 8
+    p27 = capi.make_params(64, 64, 64, dtype=capi.LBM_F32, stencil=27)
+    assert capi.lbm_state_bytes(p27) == 27 * capi.lbm_qstride(p27) * 4
 
 
 BAD = [
@@ -76,6 +79,7 @@ BAD = [
     (dict(dtype=0, adjoint_dtype=1), "adjoint_dtype"),
     (dict(dtype=1, adjoint_dtype=0), "adjoint_dtype"),
     (dict(dtype=3, scale=3.0), "power of two"),
+    (dict(stencil=15), "stencil"),
 ]
 
 

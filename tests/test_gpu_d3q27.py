@@ -1,0 +1,99 @@
+"""GPU parity of the D3Q27 stream-collide path (Sec. 2.3; the equilibrium is
+the moment-matched one of Sec. 3.1) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from _helpers import assert_f64_parity, case, dev, host, lattice, random_blobs, reduced_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("pattern", ["two_grid", "aa"])
+def test_d3q27_taylor_green_fp64(pattern):
+    u0 = lbm_inputs.taylor_green(24, 0.05)
+    cfg, kw = case(24, 24, 24, omega=1.25, stencil=27)
+    lat = lattice(cfg, kw, u0, pattern=pattern)
+    f = oracle.init(cfg, u0)
+    for n in (1, 19, 30):
+        lat.step(n)
+        f = oracle.step(cfg, f, n)
+        assert_f64_parity(host(lat.get_pdfs()), f, f"{n}")
+    rho, u = lat.moments()
+    rho_o, u_o = oracle.moments(cfg, f)
+    np.testing.assert_allclose(host(rho), rho_o, rtol=1e-12)
+    np.testing.assert_allclose(host(u), u_o, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("pattern", ["two_grid", "aa"])
+@pytest.mark.parametrize("trt", [False, True], ids=["SRT", "TRT"])
+def test_d3q27_ragged_walls_obstacles_fp64(trt, pattern):
+    solid = random_blobs((17, 21, 35), seed=50)
+    cfg, kw = case(35, 21, 17, periodic=(1, 0, 0), trt=trt, omega=1.7,
+                   accel=(2e-4, -1e-4, 5e-5), solid=solid, stencil=27)
+    u0 = np.random.default_rng(51).uniform(-0.05, 0.05, size=(3,) + cfg.shape)
+    lat = lattice(cfg, kw, u0, pattern=pattern)
+    f = oracle.init(cfg, u0)
+    for n in (11, 1):
+        lat.step(n)
+        f = oracle.step(cfg, f, n)
+        assert_f64_parity(host(lat.get_pdfs()), f, f"{n}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f32s", "f16s", "bf16s"])
+def test_d3q27_reduced_precision_one_step(dtype):
+    solid = random_blobs((16, 20, 66), seed=52)
+    cfg, kw = case(66, 20, 16, periodic=(1, 0, 1), trt=True, omega=1.95, accel=(2e-6, 0, 0),
+                   solid=solid, stencil=27)
+    u0 = lbm_inputs.shear_waves(cfg.shape, seed=53, amax=0.08)
+    lat = lattice(cfg, kw, u0, dtype=dtype)
+    lat.step(3)
+    f_in = host(lat.get_pdfs())
+    lat.step(1)
+    want = oracle.step(cfg, f_in, 1)
+    ratio = np.abs(host(lat.get_pdfs()) - want) / reduced_bound(want, dtype, lat.scale)
+    assert ratio.max() <= 1.0, ratio.max()
+
+
+def test_d3q27_aa_equals_two_grid_bitwise():
+    cfg, kw = case(40, 18, 14, periodic=(1, 0, 1), trt=True, omega=1.9, stencil=27,
+                   solid=random_blobs((14, 18, 40), seed=54))
+    u0 = lbm_inputs.shear_waves(cfg.shape, seed=55, amax=0.05)
+    a = lattice(cfg, kw, u0, dtype="f32", pattern="two_grid")
+    b = lattice(cfg, kw, u0, dtype="f32", pattern="aa")
+    a.step(7)
+    b.step(7)
+    np.testing.assert_array_equal(host(a.get_pdfs()), host(b.get_pdfs()))
+
+
+def test_d3q27_256_f32_sampled():
+    n = 256
+    cfg, kw = case(n, n, n, trt=True, omega=1.8, stencil=27)
+    lat = lattice(cfg, kw, lbm_inputs.shear_waves((n, n, n), seed=0), dtype="f32")
+    lat.step(3)
+    f_in = host(lat.get_pdfs())
+    lat.step(1)
+    cells = np.sort(np.random.default_rng(56).choice(n ** 3, 3000, replace=False))
+    got = host(lat.get_pdfs().view(27, -1)[:, torch.as_tensor(cells, device="cuda")])
+    want = oracle.step_cells(cfg, f_in, cells).T
+    assert np.all(np.abs(got - want) <= reduced_bound(want, "f32", 1.0))
+
+
+def test_d3q27_has_no_adjoint():
+    from paper_1803_04937_amd import LBMError, capi
+    cfg, kw = case(8, 8, 8, stencil=27)
+    lat = lattice(cfg, kw, np.zeros((3,) + cfg.shape), dtype="f32")
+    lam = torch.zeros((19, lat.qstride), dtype=torch.float32, device="cuda")
+    with pytest.raises(LBMError) as e:
+        lat.adjoint_step(lat.state, lam, lam.clone())
+    assert e.value.status == capi.LBM_ESTATE
+
+
+def test_d3q27_duct_has_no_spurious_current():
+    """Sec. 5.1: D3Q27 keeps the transverse velocity at rounding level."""
+    from paper_1803_04937_amd.experiments import duct_spurious_current
+    for D in (25, 45):
+        r = duct_spurious_current(D, 4 / 25, "standard", stencil=27)
+        assert r["ratio"] < 1e-13, r

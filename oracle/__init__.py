@@ -76,6 +76,7 @@ def _load():
         lib.oracle_objective.argtypes = [cfgp, P, ctypes.c_int, P, P, P]
         lib.oracle_objective.restype = ctypes.c_double
         lib.oracle_init_vjp.argtypes = [cfgp, P, P, P, P]
+        lib.oracle_init_vjp.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -98,7 +99,7 @@ class Config:
     ny: int
     nz: int
     periodic: tuple = (1, 1, 1)
-    improved: bool = True
+    improved: int = 1          # 0: D3Q19-S, 1: D3Q19-I, 2: D3Q19-I to O(u^3)
     trt: bool = False
     compressible: bool = False
     omega: float = 1.0
@@ -227,7 +228,8 @@ def adjoint_step(cfg: Config, f_t, lam_next):
     rc = lib.oracle_adjoint_step(ref, _ptr(cfg._solid()), _ptr(f_t), _ptr(lam_next),
                                  _ptr(lam_prev), _ptr(grad))
     if rc != 0:
-        raise ValueError("the oracle adjoint covers the incompressible form only")
+        raise ValueError("the oracle adjoint covers the incompressible D3Q19 form with the "
+                         "second-order equilibria only")
     return lam_prev, grad
 
 
@@ -248,7 +250,9 @@ def init_vjp(cfg: Config, u_init, lam0):
     lam0 = _f64(lam0, (NQ,) + cfg.shape)
     g = np.empty((3,) + cfg.shape)
     ref, _keep = cfg._c()
-    lib.oracle_init_vjp(ref, _ptr(cfg._solid()), _ptr(u), _ptr(lam0), _ptr(g))
+    rc = lib.oracle_init_vjp(ref, _ptr(cfg._solid()), _ptr(u), _ptr(lam0), _ptr(g))
+    if rc != 0:
+        raise ValueError("the oracle adjoint covers D3Q19 with the second-order equilibria only")
     return g
 
 

@@ -17,6 +17,11 @@
  *   standard equilibrium ......... Sec. 2.2, eq. discreteEquilibriumStandard,
  *                                  second-order part, rho0 from Sec. 2.3
  *   improved equilibrium ......... Sec. 3.2, eq. new_d3q19_equilibrium
+ *   third-order D3Q19-I .......... Sec. 3.2 construction carried to O(u^3):
+ *                                  the 19 kept Maxwellian moments, truncated
+ *                                  at third order in u, solved for f^eq with
+ *                                  the 19 x 19 moment matrix (Table 1, D3Q19-I
+ *                                  column, lists these moments)
  *   D3Q27 equilibrium ............ Sec. 3.1: moment matching on D3Q27 gives
  *                                  the standard equilibrium with D3Q27
  *                                  weights, so D3Q27 uses that form
@@ -76,7 +81,7 @@ static int opposite(int q)
 typedef struct {
     int nx, ny, nz;
     int periodic[3];    /* 1: periodic axis; 0: half-way bounce-back walls   */
-    int improved;       /* 0: D3Q19-S, 1: D3Q19-I                            */
+    int improved;       /* 0: D3Q19-S, 1: D3Q19-I, 2: D3Q19-I to O(u^3)     */
     int trt;            /* 0: SRT, 1: TRT                                    */
     int compressible;   /* 0: rho0 = 1 (the paper's choice), 1: rho0 = rho   */
     double omega;       /* SRT rate, or TRT even rate omega_plus             */
@@ -152,10 +157,133 @@ static double feq_improved(const oracle_cfg *cfg, int q, double rho, double rho0
     return rho * weight(q) + weight(q) * rho0 * bracket;
 }
 
+/* Moment-matching construction (Sec. 3.1-3.2) at third order in u.  The
+ * independent moments are xi_0^e0 xi_1^e1 xi_2^e2 with e_i in {0, 1, 2};
+ * D3Q19 keeps the 19 that are not in eq. dropped_d3q19_moments. */
+static int kept_exponents(int e[19][3])
+{
+    static const int dropped[8][3] = {{1, 2, 2}, {2, 1, 2}, {2, 2, 1}, {1, 1, 2},
+                                      {1, 2, 1}, {2, 1, 1}, {1, 1, 1}, {2, 2, 2}};
+    int n = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) {
+                int is_dropped = 0;
+                for (int k = 0; k < 8; ++k)
+                    if (dropped[k][0] == a && dropped[k][1] == b && dropped[k][2] == c)
+                        is_dropped = 1;
+                if (!is_dropped) {
+                    e[n][0] = a;
+                    e[n][1] = b;
+                    e[n][2] = c;
+                    ++n;
+                }
+            }
+    return n;
+}
+
+/* Inverse of the 19 x 19 moment matrix M[k][q] = prod_i c_qi^e_ki, by
+ * Gauss-Jordan elimination with partial pivoting.  Computed by
+ * oracle_prepare() before any parallel region reads it. */
+static double Minv[19][19];
+static int Mexp[19][3];
+static int Minv_ready = 0;
+static void moment_matrix_inverse(void)
+{
+    if (Minv_ready) return;
+    kept_exponents(Mexp);
+    double A[19][38];
+    for (int k = 0; k < 19; ++k)
+        for (int q = 0; q < 19; ++q) {
+            double v = 1.0;
+            for (int i = 0; i < 3; ++i)
+                for (int t = 0; t < Mexp[k][i]; ++t) v *= C[q][i];
+            A[k][q] = v;
+            A[k][19 + q] = (k == q);
+        }
+    for (int col = 0; col < 19; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 19; ++r)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        for (int j = 0; j < 38; ++j) {
+            double t = A[col][j];
+            A[col][j] = A[piv][j];
+            A[piv][j] = t;
+        }
+        double d = A[col][col];
+        for (int j = 0; j < 38; ++j) A[col][j] /= d;
+        for (int r = 0; r < 19; ++r)
+            if (r != col) {
+                double m = A[r][col];
+                for (int j = 0; j < 38; ++j) A[r][j] -= m * A[col][j];
+            }
+    }
+    for (int q = 0; q < 19; ++q)
+        for (int k = 0; k < 19; ++k) Minv[q][k] = A[q][19 + k];
+    Minv_ready = 1;
+}
+
+static double ipow(double x, int n)
+{
+    double r = 1.0;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+
+/* Maxwellian moment of exponent e (variance c_s^2 = 1/3), truncated at
+ * O(u^3): product of the one-dimensional moments 1, u, u^2 + 1/3, the
+ * velocity-free part times rho, every other term times rho0. */
+static double maxwellian_moment3(const int e[3], double rho, double rho0, const double u[3])
+{
+    double coef[3][3];   /* coef[axis][power] */
+    for (int i = 0; i < 3; ++i) {
+        coef[i][0] = e[i] == 0 ? 1.0 : (e[i] == 2 ? 1.0 / 3.0 : 0.0);
+        coef[i][1] = e[i] == 1 ? 1.0 : 0.0;
+        coef[i][2] = e[i] == 2 ? 1.0 : 0.0;
+    }
+    double free = coef[0][0] * coef[1][0] * coef[2][0];
+    double rest = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) {
+                if (a + b + c == 0 || a + b + c > 3) continue;
+                rest += coef[0][a] * coef[1][b] * coef[2][c] * ipow(u[0], a) * ipow(u[1], b) *
+                        ipow(u[2], c);
+            }
+    return free * rho + rest * rho0;
+}
+
+/* All 19 values f^eq = M^-1 m(rho, u). */
+static void feq_improved3_all(double rho, double rho0, const double u[3], double out[19])
+{
+    double m[19];
+    for (int k = 0; k < 19; ++k) m[k] = maxwellian_moment3(Mexp[k], rho, rho0, u);
+    for (int q = 0; q < 19; ++q) {
+        double v = 0.0;
+        for (int k = 0; k < 19; ++k) v += Minv[q][k] * m[k];
+        out[q] = v;
+    }
+}
+
 static double feq(const oracle_cfg *cfg, int q, double rho, double rho0, const double u[3])
 {
+    if (cfg->stencil != 27 && cfg->improved == 2) {
+        double all[19];
+        feq_improved3_all(rho, rho0, u, all);
+        return all[q];
+    }
     if (cfg->stencil == 27) return feq_standard(cfg, q, rho, rho0, u);
     return cfg->improved ? feq_improved(cfg, q, rho, rho0, u) : feq_standard(cfg, q, rho, rho0, u);
+}
+
+static void feq_all(const oracle_cfg *cfg, double rho, double rho0, const double u[3],
+                    double out[NQ])
+{
+    if (cfg->stencil != 27 && cfg->improved == 2) {
+        feq_improved3_all(rho, rho0, u, out);
+        return;
+    }
+    for (int q = 0; q < QN(cfg); ++q) out[q] = feq(cfg, q, rho, rho0, u);
 }
 
 /* d f^eq_q / d u_b at fixed rho and rho0, differentiated by hand from the two
@@ -173,9 +301,14 @@ static double dfeq_du(const oracle_cfg *cfg, int q, int b, double rho0, const do
     return weight(q) * rho0 * (3.0 * cb - 3.0 * u[b] * cb * cb + 9.0 * cu * cb);
 }
 
+/* Serial set-up before any parallel region (the third-order construction's
+ * moment-matrix inverse). */
+static void oracle_prepare(void) { moment_matrix_inverse(); }
+
 void oracle_feq(const oracle_cfg *cfg, double rho, double rho0, const double *u, double *out)
 {
-    for (int q = 0; q < QN(cfg); ++q) out[q] = feq(cfg, q, rho, rho0, u);
+    oracle_prepare();
+    feq_all(cfg, rho, rho0, u, out);
 }
 
 void oracle_dfeq_du(const oracle_cfg *cfg, double rho0, const double *u, double *out /*[19][3]*/)
@@ -263,7 +396,7 @@ static void collide(const oracle_cfg *cfg, const double g[NQ], double out[NQ])
 {
     double rho, rho0, u[3], fe[NQ];
     macroscopic(cfg, g, &rho, &rho0, u);
-    for (int q = 0; q < QN(cfg); ++q) fe[q] = feq(cfg, q, rho, rho0, u);
+    feq_all(cfg, rho, rho0, u, fe);
     double w = cfg->omega;
     if (!cfg->trt) {
         for (int q = 0; q < QN(cfg); ++q)
@@ -288,6 +421,7 @@ static void collide(const oracle_cfg *cfg, const double g[NQ], double out[NQ])
 void oracle_init(const oracle_cfg *cfg, const uint8_t *solid, const double *rho_init,
                  const double *u_init, double *f)
 {
+    oracle_prepare();
     int64_t n = ncells_of(cfg);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
@@ -298,13 +432,16 @@ void oracle_init(const oracle_cfg *cfg, const uint8_t *solid, const double *rho_
         double u[3] = {u_init[c], u_init[n + c], u_init[2 * n + c]};
         double rho = rho_init ? rho_init[c] : 1.0;
         double rho0 = cfg->compressible ? rho : 1.0;
-        for (int q = 0; q < QN(cfg); ++q) f[q * n + c] = feq(cfg, q, rho, rho0, u);
+        double fe[NQ];
+        feq_all(cfg, rho, rho0, u, fe);
+        for (int q = 0; q < QN(cfg); ++q) f[q * n + c] = fe[q];
     }
 }
 
 /* One two-grid pull step, fin -> fout.  Solid cells keep their values. */
 void oracle_step(const oracle_cfg *cfg, const uint8_t *solid, const double *fin, double *fout)
 {
+    oracle_prepare();
     int64_t n = ncells_of(cfg);
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < cfg->nz; ++z)
@@ -336,6 +473,7 @@ void oracle_run(const oracle_cfg *cfg, const uint8_t *solid, double *f, double *
 void oracle_step_cells(const oracle_cfg *cfg, const uint8_t *solid, const double *fin,
                        const int64_t *cells, int64_t ncell_list, double *out)
 {
+    oracle_prepare();
     int64_t n = ncells_of(cfg);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < ncell_list; ++k) {
@@ -440,11 +578,12 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
 
 /* lam_prev = (d step / d f_t)^T lam_next.  grad[0] += dJ/domega,
  * grad[1..3] += dJ/da (the contribution of this step).  Returns -1 for the
- * compressible form and for D3Q27, which have no adjoint here. */
+ * compressible form, D3Q27 and the third-order equilibrium, which have no
+ * adjoint here. */
 int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const double *f_t,
                         const double *lam_next, double *lam_prev, double *grad)
 {
-    if (cfg->compressible || cfg->stencil == 27) return -1;
+    if (cfg->compressible || cfg->stencil == 27 || cfg->improved == 2) return -1;
     int64_t n = ncells_of(cfg);
     double *plane = (double *)calloc((size_t)cfg->nz * 4, sizeof(double));
 #pragma omp parallel for schedule(static)
@@ -528,9 +667,10 @@ double oracle_objective(const oracle_cfg *cfg, const uint8_t *solid, int kind, c
 
 /* Gradient with respect to u_init of the initial state f = f^eq(rho_init,
  * u_init): grad_u[b][x] = sum_q lam0_q(x) d f^eq_q / d u_b. */
-void oracle_init_vjp(const oracle_cfg *cfg, const uint8_t *solid, const double *u_init,
-                     const double *lam0, double *grad_u)
+int oracle_init_vjp(const oracle_cfg *cfg, const uint8_t *solid, const double *u_init,
+                    const double *lam0, double *grad_u)
 {
+    if (cfg->stencil == 27 || cfg->improved == 2) return -1;
     int64_t n = ncells_of(cfg);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
@@ -545,4 +685,5 @@ void oracle_init_vjp(const oracle_cfg *cfg, const uint8_t *solid, const double *
             grad_u[b * n + c] = v;
         }
     }
+    return 0;
 }

@@ -246,3 +246,40 @@ def test_projection_property_of_improved_equilibrium():
                 np.testing.assert_allclose(vec, base, rtol=0, atol=1e-16)
             else:
                 assert np.abs(vec - base).max() > 1e-4
+
+
+# --------------------------------------------------------------------------
+# Third-order D3Q19-I (the Sec. 3.2 construction carried to O(u^3))
+# --------------------------------------------------------------------------
+
+def test_third_order_improved_matches_table1_to_third_order():
+    """All 27 moments of the third-order D3Q19-I equilibrium equal the D3Q19-I
+    column of Table 1 (which lists terms up to O(u^3))."""
+    table = _expand_table1(2)
+    c, _, _ = oracle.velocity_set()
+    cfg = oracle.Config(1, 1, 1, improved=2)
+    rng = np.random.default_rng(30)
+    for _ in range(5):
+        rho, rho0 = 1.0 + 0.2 * rng.standard_normal(2)
+        u = 0.2 * rng.standard_normal(3)
+        f = oracle.feq(cfg, rho, u, rho0=rho0)
+        for e, expr in table.items():
+            got = _discrete_moment(f, c, e)
+            want = _truncate_num(expr, 3, rho, rho0, u)
+            assert abs(got - want) < 1e-15, (e, got, want)
+
+
+def test_third_order_improved_adds_only_cubic_odd_terms():
+    """f3(t u) - f2(t u) scales as t^3 and is odd in c (the second-order part
+    is the paper's eq. new_d3q19_equilibrium)."""
+    c, _, opp = oracle.velocity_set()
+    u = np.array([0.07, -0.04, 0.05])
+    d = []
+    for t in (1.0, 2.0):
+        f3 = oracle.feq(oracle.Config(1, 1, 1, improved=2), 1.1, t * u)
+        f2 = oracle.feq(oracle.Config(1, 1, 1, improved=1), 1.1, t * u)
+        d.append(f3 - f2)
+    # rounding of O(1/3) values: 1e-15
+    np.testing.assert_allclose(d[1], 8 * d[0], rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(d[0] + d[0][opp], 0.0, atol=1e-15)
+    assert np.abs(d[0]).max() > 1e-6

@@ -57,6 +57,10 @@ MUTANTS = [
     ("D3Q27 takes the D3Q19-I form",
      "if (cfg->stencil == 27) return feq_standard(cfg, q, rho, rho0, u);",
      "if (cfg->stencil == 27) return feq_improved(cfg, q, rho, rho0, u);"),
+    ("third-order construction truncated at O(u^2)", "if (a + b + c == 0 || a + b + c > 3) continue;",
+     "if (a + b + c == 0 || a + b + c > 2) continue;"),
+    ("third-order construction drops the wrong moment", "{1, 2, 1}, {2, 1, 1}, {1, 1, 1}, {2, 2, 2}};",
+     "{1, 2, 1}, {2, 1, 1}, {1, 1, 1}, {0, 2, 2}};"),
     ("init VJP reads the rest population only", "v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);",
      "v += lam0[c] * dfeq_du(cfg, q, b, 1.0, u);"),
 ]

@@ -70,7 +70,11 @@ typedef enum {
  * (Sec. 2.2) with D3Q19 weights (D3Q19-S).  IMPROVED: eq.
  * new_d3q19_equilibrium (Sec. 3.2), built by matching 19 Maxwellian moments
  * (D3Q19-I).  Both use rho0 = 1 unless compressible is set (Sec. 2.3). */
-enum { LBM_EQ_STANDARD = 0, LBM_EQ_IMPROVED = 1 };
+enum { LBM_EQ_STANDARD = 0, LBM_EQ_IMPROVED = 1,
+       /* IMPROVED3: the same construction carried to third order in u, i.e.
+        * the equilibrium whose moments are the D3Q19-I column of Table 1
+        * (Sec. 3.1) including its O(u^3) terms.  Forward path only. */
+       LBM_EQ_IMPROVED3 = 2 };
 
 /* Collision.  SRT: eq. lb_srt_with_forces (Sec. 2.3).  TRT: two relaxation
  * rates, omega (even part) and omega_minus (odd part) with

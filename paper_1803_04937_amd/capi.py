@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
-LBM_EQ_STANDARD, LBM_EQ_IMPROVED = 0, 1
+LBM_EQ_STANDARD, LBM_EQ_IMPROVED, LBM_EQ_IMPROVED3 = 0, 1, 2
 LBM_SRT, LBM_TRT = 0, 1
 LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3, 4
 LBM_TWO_GRID, LBM_AA = 0, 1

@@ -174,6 +174,7 @@ hipError_t launch_adjoint(const Geom &g, int dtype, int ltype, int eq, bool gen,
                           void *lam_prev, double *grad, const Scratch &sc, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
     const bool want = grad != nullptr;
+    if (eq != LBM_EQ_STANDARD && eq != LBM_EQ_IMPROVED) return hipErrorInvalidValue;
 #define LBM_ADJ(DT, LT, EQ, GEN, GRAD, COLL)                                                     \
     hipLaunchKernelGGL((k_adjoint<DT, LT, EQ, GEN, GRAD>), grid, block, 0, st, g, COLL,          \
                        (const typename Store<DT>::T *)state, (const typename Lam<LT>::T *)lam_next, \

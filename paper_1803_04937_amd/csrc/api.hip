@@ -88,7 +88,8 @@ static int validate(const lbm_params *p, std::string &why) {
             why = "periodic[] entries must be 0 or 1";
             return LBM_EINVAL;
         }
-    if (p->equilibrium != LBM_EQ_STANDARD && p->equilibrium != LBM_EQ_IMPROVED) {
+    if (p->equilibrium != LBM_EQ_STANDARD && p->equilibrium != LBM_EQ_IMPROVED &&
+        p->equilibrium != LBM_EQ_IMPROVED3) {
         why = "unknown equilibrium";
         return LBM_EINVAL;
     }
@@ -450,7 +451,8 @@ extern "C" int lbm_set_rates(lbm_ctx *c, double omega, const double *accel) {
 extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next,
                                 void *lam_prev, double *grad) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19) return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19");
+    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3)
+        return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19 with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
     if (!state_t || !lam_next || !lam_prev || lam_next == lam_prev)
@@ -463,7 +465,8 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam
 
 extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *out, void *lam) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19) return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19");
+    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3)
+        return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19 with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "objectives are defined for the incompressible form only");
     if (kind != LBM_OBJ_KINETIC_ENERGY && kind != LBM_OBJ_OUTLET_FLUX)
@@ -477,7 +480,8 @@ extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *ou
 
 extern "C" int lbm_init_vjp(lbm_ctx *c, const double *u_init, const void *lam0, double *grad_u) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19) return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19");
+    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3)
+        return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19 with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
     if (!u_init || !lam0 || !grad_u) return fail(c, LBM_EINVAL, "u_init, lam0, grad_u must be set");

@@ -20,15 +20,23 @@ template <int EQ, int QN>
 __device__ __forceinline__ void shifted_feq(double drho, double rho0, double ux, double uy,
                                             double uz, double (&d)[QN]) {
     constexpr int NP = (QN - 1) / 2;
-    double cu[NP], E[NP], E0;
+    double cu[NP], E[NP], E0, O[NP];
     Poly::even<double, EQ, NP>(ux, uy, uz, cu, E, E0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) O[p] = 3.0 * cu[p];
+    if constexpr (EQ == LBM_EQ_IMPROVED3 && NP == 9) {
+        double O3[9];
+        Poly::odd3<double>(ux, uy, uz, cu, O3);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) O[p] += O3[p];
+    }
     d[0] = wq(QN, 0) * (drho + rho0 * E0);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const int q = 2 * p + 1;
         const double w = wq(QN, q);
-        d[q] = w * (drho + rho0 * (E[p] + 3.0 * cu[p]));
-        d[q + 1] = w * (drho + rho0 * (E[p] - 3.0 * cu[p]));
+        d[q] = w * (drho + rho0 * (E[p] + O[p]));
+        d[q + 1] = w * (drho + rho0 * (E[p] - O[p]));
     }
 }
 
@@ -378,6 +386,7 @@ const Coll<float> &pick<LBM_BF16_SHIFTED>(const CollBoth &P) { return P.f; }
 #define LBM_DISPATCH_EQ(eq, BODY)                                                              \
     if (qn == 27) { constexpr int QN = 27; constexpr int EQ = LBM_EQ_STANDARD; BODY; }         \
     else if (eq == LBM_EQ_IMPROVED) { constexpr int QN = 19; constexpr int EQ = LBM_EQ_IMPROVED; BODY; } \
+    else if (eq == LBM_EQ_IMPROVED3) { constexpr int QN = 19; constexpr int EQ = LBM_EQ_IMPROVED3; BODY; } \
     else { constexpr int QN = 19; constexpr int EQ = LBM_EQ_STANDARD; BODY; }
 
 #define LBM_DISPATCH_Q(BODY)                              \

@@ -323,6 +323,26 @@ __device__ __forceinline__ void moments(const R (&d)[QN], R &drho, R &jx, R &jy,
 struct Poly {
     // NP = (QN - 1) / 2 pairs; D3Q27 has the standard form only (Sec. 3.1:
     // moment matching on D3Q27 gives it).
+    // Cubic odd terms of the third-order improved equilibrium, per pair
+    // (f^eq gains w rho0 O3 on q = 2p + 1 and -w rho0 O3 on its opposite):
+    // axis a: -9 u_a (u^2 - u_a^2); edge (a, b) with signs (s_a, s_b):
+    // 9 (s_a u_a)(s_b u_b)(c . u).  Derived by the moment-matching
+    // construction of Sec. 3.2 at O(u^3).
+    template <typename R>
+    static __device__ __forceinline__ void odd3(R ux, R uy, R uz, const R (&cu)[9], R (&O3)[9]) {
+        const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+        O3[0] = R(-9) * ux * (uy2 + uz2);
+        O3[1] = R(-9) * uy * (ux2 + uz2);
+        O3[2] = R(-9) * uz * (ux2 + uy2);
+        const R xy = R(9) * ux * uy, xz = R(9) * ux * uz, yz = R(9) * uy * uz;
+        O3[3] = xy * cu[3];
+        O3[4] = -xy * cu[4];
+        O3[5] = xz * cu[5];
+        O3[6] = -xz * cu[6];
+        O3[7] = yz * cu[7];
+        O3[8] = -yz * cu[8];
+    }
+
     template <typename R, int EQ, int NP = 9>
     static __device__ __forceinline__ void even(R ux, R uy, R uz, R (&cu)[NP], R (&E)[NP], R &E0) {
         const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz, uu = ux2 + uy2 + uz2;
@@ -341,7 +361,7 @@ struct Poly {
             cu[11] = (ux - uy) + uz;
             cu[12] = (uy - ux) + uz;
         }
-        if (EQ == LBM_EQ_IMPROVED && NP == 9) {
+        if ((EQ == LBM_EQ_IMPROVED || EQ == LBM_EQ_IMPROVED3) && NP == 9) {
             E0 = -uu;
             E[0] = R(6) * ux2 - R(3) * uu;
             E[1] = R(6) * uy2 - R(3) * uu;
@@ -375,8 +395,16 @@ __device__ __forceinline__ void collide(R (&d)[QN], const Coll<R> &P) {
         inv = R(1) / rho0;
     }
     const R ux = (jx + P.ah[0]) * inv, uy = (jy + P.ah[1]) * inv, uz = (jz + P.ah[2]) * inv;
-    R cu[NP], E[NP], E0;
+    R cu[NP], E[NP], E0, O[NP];
     Poly::even<R, EQ, NP>(ux, uy, uz, cu, E, E0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) O[p] = R(3) * cu[p];
+    if constexpr (EQ == LBM_EQ_IMPROVED3 && NP == 9) {
+        R O3[9];
+        Poly::odd3<R>(ux, uy, uz, cu, O3);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) O[p] += O3[p];
+    }
     const R w0 = R(wq(QN, 0));
     d[0] = d[0] - P.wp * (d[0] - w0 * (drho + rho0 * E0));
 #pragma unroll
@@ -384,7 +412,7 @@ __device__ __forceinline__ void collide(R (&d)[QN], const Coll<R> &P) {
         const int q = 2 * p + 1;
         const R w = R(wq(QN, q));
         const R np = R(0.5) * (d[q] + d[q + 1]) - w * (drho + rho0 * E[p]);
-        const R nm = R(0.5) * (d[q] - d[q + 1]) - w * rho0 * (R(3) * cu[p]);
+        const R nm = R(0.5) * (d[q] - d[q + 1]) - w * rho0 * O[p];
         const R tp = P.wp * np;
         const R tm = P.wm * nm - P.fpair[p];
         d[q] = d[q] - tp - tm;

@@ -10,7 +10,8 @@ import torch
 from . import capi
 from .capi import LBMError
 
-EQUILIBRIA = {"standard": capi.LBM_EQ_STANDARD, "improved": capi.LBM_EQ_IMPROVED}
+EQUILIBRIA = {"standard": capi.LBM_EQ_STANDARD, "improved": capi.LBM_EQ_IMPROVED,
+              "improved3": capi.LBM_EQ_IMPROVED3}
 COLLISIONS = {"srt": capi.LBM_SRT, "trt": capi.LBM_TRT}
 DTYPES = {"f64": capi.LBM_F64, "f32": capi.LBM_F32, "f32s": capi.LBM_F32_SHIFTED,
           "f16s": capi.LBM_F16_SHIFTED, "bf16s": capi.LBM_BF16_SHIFTED}

@@ -43,7 +43,8 @@ def case(nx, ny, nz, periodic=(1, 1, 1), improved=True, trt=False, omega=1.2, ma
     cfg = oracle.Config(nx, ny, nz, periodic=tuple(periodic), improved=improved, trt=trt,
                         compressible=compressible, omega=omega, magic=magic, accel=tuple(accel),
                         solid=solid, stencil=stencil)
-    kw = dict(periodic=tuple(periodic), equilibrium="improved" if improved else "standard",
+    eq_name = {0: "standard", 1: "improved", 2: "improved3"}[int(improved)]
+    kw = dict(periodic=tuple(periodic), equilibrium=eq_name,
               collision="trt" if trt else "srt", compressible=compressible, omega=omega,
               trt_magic=magic, accel=tuple(accel), stencil=stencil)
     if solid is not None:

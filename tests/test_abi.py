@@ -71,7 +71,7 @@ BAD = [
     (dict(collision=1, trt_magic=-1.0), "trt_magic"),
     (dict(dtype=7), "dtype"),
     (dict(pattern=3), "pattern"),
-    (dict(equilibrium=2), "equilibrium"),
+    (dict(equilibrium=3), "equilibrium"),
     (dict(collision=5), "collision"),
     (dict(compressible=2), "compressible"),
     (dict(periodic=(1, 2, 1)), "periodic"),

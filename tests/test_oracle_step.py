@@ -321,3 +321,14 @@ def test_duct_transverse_velocity_vanishes_only_for_improved():
         out[improved] = np.abs(u[1:]).max() / np.abs(u[0]).max()
     assert out[True] < 1e-13, out
     assert out[False] > 1e-7, out
+
+
+def test_duct_third_order_improved_has_no_transverse_current():
+    """The third-order D3Q19-I equilibrium keeps the duct invariant as well."""
+    D, omega = 9, 1.0
+    nu = (1 / omega - 0.5) / 3
+    a = 10 * nu * nu / (0.07 * D ** 3)
+    cfg = oracle.Config(1, D, D, periodic=(1, 0, 0), improved=2, omega=omega, accel=(a, 0, 0))
+    f = oracle.step(cfg, oracle.init(cfg, np.zeros((3,) + cfg.shape)), 1500)
+    _, u = oracle.moments(cfg, f)
+    assert np.abs(u[1:]).max() / np.abs(u[0]).max() < 1e-13

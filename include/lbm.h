@@ -190,6 +190,12 @@ int lbm_moments(lbm_ctx *c, double *rho, double *u, double *sums);
  * no padding), f*_q in FP64 whatever the dtype and AA parity. */
 int lbm_get_pdfs(lbm_ctx *c, double *canonical);
 
+/* Canonical f*_q (FP64) of the current state at n listed cells: cells is a
+ * device int64 [n] of cell indices, out a device double [n][Q].  Indices
+ * outside the lattice give NaN rows.  For probing states too large to copy
+ * whole. */
+int lbm_sample_pdfs(lbm_ctx *c, const int64_t *cells, int64_t n, double *out);
+
 /* Overwrite the current state from a canonical device double [Q][cells]
  * (quantised with the context's scale).  Solid cells are set to w_q. */
 int lbm_set_pdfs(lbm_ctx *c, const double *canonical);

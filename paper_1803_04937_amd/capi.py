@@ -29,7 +29,7 @@ EXPORTS = [
     "lbm_version", "lbm_velocity_set", "lbm_qstride", "lbm_state_bytes", "lbm_adjoint_bytes",
     "lbm_validate", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_step",
     "lbm_stream_collide", "lbm_current_state", "lbm_copy_state", "lbm_time", "lbm_scale", "lbm_moments",
-    "lbm_get_pdfs", "lbm_set_pdfs", "lbm_watchdog", "lbm_set_rates", "lbm_adjoint_step",
+    "lbm_get_pdfs", "lbm_sample_pdfs", "lbm_set_pdfs", "lbm_watchdog", "lbm_set_rates", "lbm_adjoint_step",
     "lbm_objective", "lbm_init_vjp",
 ]
 
@@ -79,6 +79,7 @@ def _load():
         "lbm_scale": ([P], ctypes.c_double),
         "lbm_moments": ([P, P, P, P], ctypes.c_int),
         "lbm_get_pdfs": ([P, P], ctypes.c_int),
+        "lbm_sample_pdfs": ([P, P, ctypes.c_int64, P], ctypes.c_int),
         "lbm_set_pdfs": ([P, P], ctypes.c_int),
         "lbm_watchdog": ([P, ctypes.c_double], ctypes.c_int),
         "lbm_set_rates": ([P, ctypes.c_double, P], ctypes.c_int),
@@ -231,6 +232,10 @@ def lbm_moments(ctx, rho=None, u=None, want_sums: bool = False):
 
 def lbm_get_pdfs(ctx, canonical) -> None:
     _check(_lib.lbm_get_pdfs(ctx, _addr(canonical)), ctx)
+
+
+def lbm_sample_pdfs(ctx, cells, n: int, out) -> None:
+    _check(_lib.lbm_sample_pdfs(ctx, _addr(cells), int(n), _addr(out)), ctx)
 
 
 def lbm_set_pdfs(ctx, canonical) -> None:

@@ -411,6 +411,16 @@ extern "C" int lbm_get_pdfs(lbm_ctx *c, double *canonical) {
     return LBM_OK;
 }
 
+extern "C" int lbm_sample_pdfs(lbm_ctx *c, const int64_t *cells, int64_t n, double *out) {
+    if (!c) return LBM_EINVAL;
+    if (n < 0 || (n > 0 && (!cells || !out))) return fail(c, LBM_EINVAL, "cells/out must be set, n >= 0");
+    if (n > ((int64_t)1 << 40)) return fail(c, LBM_EINVAL, "n too large");
+    hipError_t e = launch_sample(c->g, c->p.stencil, c->p.dtype, layout_of(c), 1.0 / c->scale,
+                                 state_of(c), cells, n, out, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "sample_pdfs");
+    return LBM_OK;
+}
+
 extern "C" int lbm_set_pdfs(lbm_ctx *c, const double *canonical) {
     if (!c) return LBM_EINVAL;
     if (!canonical) return fail(c, LBM_EINVAL, "canonical is NULL");

@@ -224,6 +224,37 @@ __global__ __launch_bounds__(kBlock) void k_get(Geom g, Layout layout, double in
     }
 }
 
+// Canonical f*_q at a list of cells: out[k * QN + q].  Indices outside the
+// lattice yield NaN (no out-of-range access).
+template <int QN, int DT>
+__global__ __launch_bounds__(kBlock) void k_sample(Geom g, Layout layout, double inv_s,
+                                                   const typename Store<DT>::T *__restrict__ A,
+                                                   const int64_t *__restrict__ cells, int64_t n,
+                                                   double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int64_t c = cells[k];
+    if (c < 0 || c >= (int64_t)g.ncells) {
+#pragma unroll
+        for (int q = 0; q < QN; ++q) out[k * QN + q] = __builtin_nan("");
+        return;
+    }
+    const uint32_t idx = (uint32_t)c;
+    const bool solid = is_solid(g, idx);
+    const Hood h = make_hood(idx, g);
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+        double v = wq(QN, q);
+        if (!solid) {
+            int arr;
+            uint32_t cell;
+            canonical_slot<true>(h, g, layout, q, arr, cell);
+            v = load_canonical<DT>(A + arr * g.qstride, cell, wq(QN, q), inv_s);
+        }
+        out[k * QN + q] = v;
+    }
+}
+
 template <int QN, int DT>
 __global__ __launch_bounds__(kBlock) void k_set(Geom g, Layout layout, double s,
                                                 const double *__restrict__ in,
@@ -454,6 +485,19 @@ hipError_t launch_get(const Geom &g, int qn, int dtype, Layout layout, double in
         using T = typename Store<DT>::T;
         hipLaunchKernelGGL((k_get<QN, DT>), grid, block, 0, st, g, layout, inv_s, (const T *)A,
                            out);
+    }));
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const Geom &g, int qn, int dtype, Layout layout, double inv_s,
+                         const void *A, const int64_t *cells, int64_t n, double *out,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((uint32_t)((n + kBlock - 1) / kBlock)), block(kBlock);
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_Q({
+        using T = typename Store<DT>::T;
+        hipLaunchKernelGGL((k_sample<QN, DT>), grid, block, 0, st, g, layout, inv_s,
+                           (const T *)A, cells, n, out);
     }));
     return hipGetLastError();
 }

@@ -46,6 +46,9 @@ hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool gen, bo
                           const CollBoth &P, void *A, hipStream_t st);
 hipError_t launch_get(const Geom &g, int qn, int dtype, Layout layout, double inv_s, const void *A,
                       double *out, hipStream_t st);
+hipError_t launch_sample(const Geom &g, int qn, int dtype, Layout layout, double inv_s,
+                         const void *A, const int64_t *cells, int64_t n, double *out,
+                         hipStream_t st);
 hipError_t launch_set(const Geom &g, int qn, int dtype, Layout layout, double s, const double *in,
                       void *A, hipStream_t st);
 hipError_t launch_moments(const Geom &g, int qn, int dtype, Layout layout, double inv_s,

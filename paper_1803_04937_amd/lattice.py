@@ -140,6 +140,13 @@ class Lattice:
         capi.lbm_get_pdfs(self.ctx, out)
         return out
 
+    def sample_pdfs(self, cells) -> torch.Tensor:
+        """Canonical f*_q at the given flat cell indices: tensor (n, Q) FP64."""
+        cells = torch.as_tensor(cells, dtype=torch.int64).to(self.device).contiguous()
+        out = torch.empty((cells.numel(), self.q), dtype=torch.float64, device=self.device)
+        capi.lbm_sample_pdfs(self.ctx, cells, cells.numel(), out)
+        return out
+
     def set_pdfs(self, f) -> None:
         f = torch.as_tensor(f).to(self.device, torch.float64).contiguous()
         assert f.shape == (self.q,) + self.shape

@@ -54,10 +54,19 @@ __host__ __device__ constexpr double wq(int qn, int q) {
 // ---------------------------------------------------------------------------
 // Measured on MI355X at 256^3 FP32: the forward pull is faster (+2 %) with
 // ordinary loads for its x-shifted directions, the adjoint (which also
-// streams lam) is faster (+6 %) with the hint on every access.
-constexpr bool kNtShiftedLoadsForward = false;
-constexpr bool kNtShiftedLoadsAdjoint = true;
-constexpr bool kNtShiftedStores = true;
+// streams lam) is faster (+6 %) with the hint on every load.
+#ifndef LBM_NT_FWD_SHIFTED_LOADS
+#define LBM_NT_FWD_SHIFTED_LOADS 0
+#endif
+#ifndef LBM_NT_ADJ_SHIFTED_LOADS
+#define LBM_NT_ADJ_SHIFTED_LOADS 1
+#endif
+#ifndef LBM_NT_SHIFTED_STORES
+#define LBM_NT_SHIFTED_STORES 1
+#endif
+constexpr bool kNtShiftedLoadsForward = LBM_NT_FWD_SHIFTED_LOADS;
+constexpr bool kNtShiftedLoadsAdjoint = LBM_NT_ADJ_SHIFTED_LOADS;
+constexpr bool kNtShiftedStores = LBM_NT_SHIFTED_STORES;
 
 template <typename T>
 __device__ __forceinline__ T ld(const T *p, bool nt = true) {

@@ -48,6 +48,8 @@ class _Cfg(ctypes.Structure):
         ("omega", ctypes.c_double), ("magic", ctypes.c_double),
         ("accel", ctypes.c_double * 3),
         ("stencil", ctypes.c_int),
+        ("mrt", ctypes.c_int),
+        ("omega3", ctypes.c_double), ("omega4", ctypes.c_double),
     ]
 
 
@@ -107,6 +109,9 @@ class Config:
     accel: tuple = (0.0, 0.0, 0.0)
     solid: np.ndarray | None = field(default=None, repr=False)
     stencil: int = 19
+    mrt: bool = False
+    omega3: float = 1.0
+    omega4: float = 1.0
 
     @property
     def shape(self):
@@ -132,6 +137,9 @@ class Config:
         c.omega = float(self.omega)
         c.magic = float(self.magic)
         c.stencil = int(self.stencil)
+        c.mrt = int(self.mrt)
+        c.omega3 = float(self.omega3)
+        c.omega4 = float(self.omega4)
         return ctypes.byref(c), c
 
     def _solid(self):

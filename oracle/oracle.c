@@ -30,6 +30,12 @@
  *   macroscopic moments .......... Sec. 2.3, eqs. mass_conservation and
  *                                  macroscopic_vel_shift
  *   half-way bounce-back, periodic Sec. 5.1 (duct set-up)
+ *   MRT collision ................ Sec. 3.2: C = -M^-1 S (M f - m_eq) in the
+ *                                  space of the 19 kept monomial moments,
+ *                                  m_eq = M f^eq (for D3Q19-I: the Maxwellian
+ *                                  moments); rates: 2nd-order moments omega,
+ *                                  3rd-order omega3, 4th-order omega4; force
+ *                                  M^-1 (I - S/2) M F
  *   TRT collision ................ named in Sec. 1 and Sec. 3.3 but not
  *                                  defined there; the two-relaxation-time
  *                                  split into even and odd parts over
@@ -88,6 +94,9 @@ typedef struct {
     double magic;       /* TRT Lambda = (1/w+ - 1/2)(1/w- - 1/2)             */
     double accel[3];    /* body acceleration a                               */
     int stencil;        /* 19 (D3Q19) or 27 (D3Q27)                          */
+    int mrt;            /* 1: MRT (D3Q19), overrides trt                     */
+    double omega3;      /* MRT rate of the third-order moments               */
+    double omega4;      /* MRT rate of the fourth-order moments              */
 } oracle_cfg;
 
 /* Weights by the squared length of c_q (Sec. 2.3).  D3Q19: 1/3, 1/18, 1/36.
@@ -398,6 +407,30 @@ static void collide(const oracle_cfg *cfg, const double g[NQ], double out[NQ])
     macroscopic(cfg, g, &rho, &rho0, u);
     feq_all(cfg, rho, rho0, u, fe);
     double w = cfg->omega;
+    if (cfg->mrt) {
+        /* m = M g, m_eq = M f^eq, F moments; relax moment k with its rate. */
+        double m[19], meq[19], mF[19], mnew[19];
+        for (int k = 0; k < 19; ++k) {
+            m[k] = meq[k] = mF[k] = 0.0;
+            for (int q = 0; q < 19; ++q) {
+                double mk = 1.0;
+                for (int i = 0; i < 3; ++i)
+                    for (int t = 0; t < Mexp[k][i]; ++t) mk *= C[q][i];
+                m[k] += mk * g[q];
+                meq[k] += mk * fe[q];
+                mF[k] += mk * force_term(cfg, q);
+            }
+            int order = Mexp[k][0] + Mexp[k][1] + Mexp[k][2];
+            double s = order <= 1 ? 1.0 : (order == 2 ? w : (order == 3 ? cfg->omega3 : cfg->omega4));
+            mnew[k] = m[k] - s * (m[k] - meq[k]) + (1.0 - s / 2.0) * mF[k];
+        }
+        for (int q = 0; q < 19; ++q) {
+            double v = 0.0;
+            for (int k = 0; k < 19; ++k) v += Minv[q][k] * mnew[k];
+            out[q] = v;
+        }
+        return;
+    }
     if (!cfg->trt) {
         for (int q = 0; q < QN(cfg); ++q)
             out[q] = g[q] - w * (g[q] - fe[q]) + (1.0 - w / 2.0) * force_term(cfg, q);
@@ -583,7 +616,7 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
 int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const double *f_t,
                         const double *lam_next, double *lam_prev, double *grad)
 {
-    if (cfg->compressible || cfg->stencil == 27 || cfg->improved == 2) return -1;
+    if (cfg->compressible || cfg->stencil == 27 || cfg->improved == 2 || cfg->mrt) return -1;
     int64_t n = ncells_of(cfg);
     double *plane = (double *)calloc((size_t)cfg->nz * 4, sizeof(double));
 #pragma omp parallel for schedule(static)

@@ -61,6 +61,10 @@ MUTANTS = [
      "if (a + b + c == 0 || a + b + c > 2) continue;"),
     ("third-order construction drops the wrong moment", "{1, 2, 1}, {2, 1, 1}, {1, 1, 1}, {2, 2, 2}};",
      "{1, 2, 1}, {2, 1, 1}, {1, 1, 1}, {0, 2, 2}};"),
+    ("MRT force without (1 - s/2)", "mnew[k] = m[k] - s * (m[k] - meq[k]) + (1.0 - s / 2.0) * mF[k];",
+     "mnew[k] = m[k] - s * (m[k] - meq[k]) + mF[k];"),
+    ("MRT third-order moments take the fourth-order rate",
+     "(order == 3 ? cfg->omega3 : cfg->omega4)", "(order == 3 ? cfg->omega4 : cfg->omega4)"),
     ("init VJP reads the rest population only", "v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);",
      "v += lam0[c] * dfeq_du(cfg, q, b, 1.0, u);"),
 ]

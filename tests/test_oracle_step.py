@@ -332,3 +332,81 @@ def test_duct_third_order_improved_has_no_transverse_current():
     f = oracle.step(cfg, oracle.init(cfg, np.zeros((3,) + cfg.shape)), 1500)
     _, u = oracle.moments(cfg, f)
     assert np.abs(u[1:]).max() / np.abs(u[0]).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# MRT with Maxwellian equilibrium moments (Sec. 3.2)
+# --------------------------------------------------------------------------
+
+def _mrt_base(**kw):
+    solid = np.zeros((4, 5, 6), np.uint8)
+    solid[1, 2, 2:4] = 1
+    d = dict(nx=6, ny=5, nz=4, periodic=(1, 0, 1), omega=1.4, accel=(2e-4, -1e-4, 5e-5),
+             solid=solid)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("improved", [0, 1, 2])
+def test_mrt_with_equal_rates_is_srt(improved):
+    """C_MRT with S = omega I is the BGK operator with f^eq = M^-1 m_eq."""
+    srt = oracle.Config(improved=improved, **_mrt_base())
+    mrt = oracle.Config(improved=improved, mrt=True, omega3=1.4, omega4=1.4, **_mrt_base())
+    f = _noisy_state(srt, 80)
+    np.testing.assert_allclose(oracle.step(mrt, f, 4), oracle.step(srt, f, 4), rtol=0,
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+def test_mrt_with_trt_rates_is_trt(improved):
+    """Third-order moments at omega_minus and fourth-order at omega: the even
+    and odd moment groups relax like TRT's even and odd parts."""
+    w, lam = 1.4, 3 / 16
+    wm = 1 / (0.5 + lam / (1 / w - 0.5))
+    trt = oracle.Config(improved=improved, trt=True, magic=lam, **_mrt_base())
+    mrt = oracle.Config(improved=improved, mrt=True, omega3=wm, omega4=w, **_mrt_base())
+    f = _noisy_state(trt, 81)
+    np.testing.assert_allclose(oracle.step(mrt, f, 4), oracle.step(trt, f, 4), rtol=0,
+                               atol=1e-15)
+
+
+def test_mrt_conservation_and_viscosity():
+    """Mass and momentum (+a) are conserved whatever the free rates; the shear
+    wave decays with nu = (1/omega - 1/2)/3 whatever omega3, omega4."""
+    cfg = oracle.Config(1, 1, 1, improved=1, mrt=True, omega=1.3, omega3=1.7, omega4=0.9,
+                        accel=(1e-3, 2e-4, -5e-4))
+    f = _noisy_state(cfg, 82, amp=0.05)
+    out = oracle.step(cfg, f)
+    assert abs(out.sum() - f.sum()) < 1e-15
+    dj = np.einsum("qd,q...->d...", C, out - f).ravel()
+    np.testing.assert_allclose(dj, cfg.accel, rtol=0, atol=1e-16)
+    n, omega = 32, 1.3
+    nu = (1 / omega - 0.5) / 3
+    k = 2 * np.pi / n
+    steps = int(round(0.5 / (nu * k * k)))
+    amps = []
+    for w3, w4 in ((1.3, 1.3), (1.8, 0.7)):
+        c2 = oracle.Config(1, n, 1, improved=1, mrt=True, omega=omega, omega3=w3, omega4=w4)
+        f2 = oracle.step(c2, oracle.init(c2, lbm_inputs.shear_wave(c2.shape, 1e-3)), steps)
+        _, u = oracle.moments(c2, f2)
+        amps.append(2 * (u[0][0, :, 0] * np.sin(k * np.arange(n))).mean() / 1e-3)
+    for a in amps:
+        assert abs(a - np.exp(-nu * k * k * steps)) < 5e-3
+
+
+@pytest.mark.parametrize("w3,w4", [(1.7, 0.8), (0.6, 1.5)])
+def test_mrt_maxwellian_moments_keep_the_duct_invariant(w3, w4):
+    """Sec. 3.3: the construction generalises to MRT.  With Maxwellian
+    equilibrium moments (D3Q19-I) the duct keeps u_y = u_z = 0 for any free
+    rates; with the standard equilibrium's moments it does not."""
+    D, omega = 9, 1.0
+    nu = (1 / omega - 0.5) / 3
+    a = 10 * nu * nu / (0.07 * D ** 3)
+    ratios = {}
+    for improved in (1, 0):
+        cfg = oracle.Config(1, D, D, periodic=(1, 0, 0), improved=improved, omega=omega,
+                            accel=(a, 0, 0), mrt=True, omega3=w3, omega4=w4)
+        f = oracle.step(cfg, oracle.init(cfg, np.zeros((3,) + cfg.shape)), 1500)
+        _, u = oracle.moments(cfg, f)
+        ratios[improved] = np.abs(u[1:]).max() / np.abs(u[0]).max()
+    assert ratios[1] < 1e-13 and ratios[0] > 1e-5, ratios

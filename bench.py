@@ -223,6 +223,18 @@ def main():
             "time_ratio_vs_d3q19": round(ms27 / fwd_ms, 3)}
         lat2.close()
         del lat2
+        # MRT (Sec. 3.2) in the 19 kept moments, same second-order rate
+        c = dict(common)
+        c.update(collision="mrt", mrt_omega3=1.6, mrt_omega4=1.2)
+        lat2 = Lattice(n, n, n, u=u0, dtype="f32", **c)
+        msm = timed_forward(torch, lat2, 50, 5)
+        gbs = 2 * 19 * 4 * ncells / (msm * 1e-3) / 1e9
+        extras["fwd_f32_I_mrt"] = {
+            "ms": round(msm, 5), "mlups": round(ncells / (msm * 1e-3) / 1e6, 1),
+            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "time_ratio_vs_trt": round(msm / fwd_ms, 3)}
+        lat2.close()
+        del lat2
     if copy_ms is not None:
         extras["copy_state_f32"] = {"ms": round(copy_ms, 5), "bytes": 2 * state_bytes,
                                     "GBs": round(2 * state_bytes / (copy_ms * 1e-3) / 1e9, 1)}

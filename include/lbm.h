@@ -80,8 +80,15 @@ enum { LBM_EQ_STANDARD = 0, LBM_EQ_IMPROVED = 1,
  * rates, omega (even part) and omega_minus (odd part) with
  * Lambda = (1/omega - 1/2)(1/omega_minus - 1/2) = trt_magic; the force
  * term, which is odd, takes the factor (1 - omega_minus/2).  The paper names
- * TRT (Sec. 1, Sec. 3.3) without defining it. */
-enum { LBM_SRT = 0, LBM_TRT = 1 };
+ * TRT (Sec. 1, Sec. 3.3) without defining it.  MRT (D3Q19 only): the
+ * collision C = -M^-1 S (M f - m_eq) + M^-1 (I - S/2) M F of Sec. 3.2 in the
+ * space of the 19 monomial moments that D3Q19 keeps (all xi^e with
+ * e_i in {0,1,2} except the 8 that Sec. 3.2 drops), with m_eq the moments of
+ * the chosen equilibrium (for IMPROVED: the Maxwellian ones).  Rates:
+ * second-order moments omega, third-order mrt_omega3, fourth-order
+ * mrt_omega4 (conserved moments are unaffected by their rate).  Forward path
+ * only. */
+enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2 };
 
 /* Storage types of the PDF state. */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2, LBM_F16_SHIFTED = 3,
@@ -100,7 +107,7 @@ typedef struct {
     int32_t periodic[3];      /* per axis: 1 periodic, 0 half-way bounce-back walls
                                  at both faces (Sec. 5.1)                        */
     int32_t equilibrium;      /* LBM_EQ_*                                         */
-    int32_t collision;        /* LBM_SRT / LBM_TRT                                */
+    int32_t collision;        /* LBM_SRT / LBM_TRT / LBM_MRT                      */
     int32_t dtype;            /* storage, LBM_F64 ... LBM_BF16_SHIFTED             */
     int32_t pattern;          /* LBM_TWO_GRID / LBM_AA                            */
     int32_t compressible;     /* 0: rho0 = 1 (the paper's choice); 1: rho0 = rho   */
@@ -113,6 +120,8 @@ typedef struct {
     double accel[3];          /* body acceleration a; F_q = 3 w_q c_q.a (Sec. 2.3) */
     double scale;             /* F16/BF16: s (power of two) or 0 = chosen by
                                  lbm_init from the initial state                  */
+    double mrt_omega3;        /* MRT rate of the third-order moments, (0, 2)      */
+    double mrt_omega4;        /* MRT rate of the fourth-order moments, (0, 2)     */
 } lbm_params;
 
 /* Library version string. */

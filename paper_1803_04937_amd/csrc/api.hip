@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <string>
+#include <utility>
 
 #include "launch.h"
 #include "lbm.h"
@@ -93,7 +94,7 @@ static int validate(const lbm_params *p, std::string &why) {
         why = "unknown equilibrium";
         return LBM_EINVAL;
     }
-    if (p->collision != LBM_SRT && p->collision != LBM_TRT) {
+    if (p->collision != LBM_SRT && p->collision != LBM_TRT && p->collision != LBM_MRT) {
         why = "unknown collision";
         return LBM_EINVAL;
     }
@@ -125,6 +126,17 @@ static int validate(const lbm_params *p, std::string &why) {
     if (p->collision == LBM_TRT && !(p->trt_magic > 0.0 && isfinite(p->trt_magic))) {
         why = "trt_magic must be a positive finite number";
         return LBM_EINVAL;
+    }
+    if (p->collision == LBM_MRT) {
+        if (p->stencil != 19) {
+            why = "MRT is defined for stencil 19 only";
+            return LBM_EINVAL;
+        }
+        if (!(p->mrt_omega3 > 0.0 && p->mrt_omega3 < 2.0) ||
+            !(p->mrt_omega4 > 0.0 && p->mrt_omega4 < 2.0)) {
+            why = "mrt_omega3 and mrt_omega4 must lie in (0, 2)";
+            return LBM_EINVAL;
+        }
     }
     for (int d = 0; d < 3; ++d)
         if (!isfinite(p->accel[d])) {
@@ -186,6 +198,80 @@ extern "C" int lbm_adjoint_bytes(const lbm_params *p, size_t *bytes) {
     return LBM_OK;
 }
 
+// In-place inverse of an n x n matrix (n <= 10) by Gauss-Jordan elimination
+// with partial pivoting.  The moment matrices passed here are nonsingular.
+static void invert(double *a, int n) {
+    double w[10][20];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j)
+            w[i][j] = j < n ? a[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(w[r][col]) > fabs(w[piv][col])) piv = r;
+        for (int j = 0; j < 2 * n; ++j) std::swap(w[col][j], w[piv][j]);
+        const double inv = 1.0 / w[col][col];
+        for (int j = 0; j < 2 * n; ++j) w[col][j] *= inv;
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const double f = w[r][col];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 2 * n; ++j) w[r][j] -= f * w[col][j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) a[i * n + j] = w[i][n + j];
+}
+
+// MRT relaxation matrices (Sec. 3.2) acting on the pair coordinates of the
+// collide kernel.  D3Q19 keeps the monomials xi^e, e_i in {0,1,2}, other than
+// the 8 that Sec. 3.2 drops; they split by parity into 10 even and 9 odd
+// ones.  On a non-equilibrium vector n the even moments are
+// sum_q c_q^e n_q = c_0^e n_0 + sum_p 2 c_q^e (n_q + n_qbar)/2 and the odd
+// ones sum_p 2 c_q^e (n_q - n_qbar)/2 (q = 2p+1, qbar = q+1), so
+// M_e = [c_0^e | 2 c_q^e] (10 x 10) and M_o = [2 c_q^e] (9 x 9); the
+// relaxation in pair coordinates is K = M^-1 S M.
+static void mrt_matrices(const lbm_params &p, double ke[100], double ko[81]) {
+    static const int even[10][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0},
+                                    {1, 0, 1}, {0, 1, 1}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}};
+    static const int odd[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 1, 0}, {2, 0, 1},
+                                  {1, 2, 0}, {0, 2, 1}, {1, 0, 2}, {0, 1, 2}};
+    auto mono = [](const int e[3], int q) {
+        const int c[3] = {kC[q].x, kC[q].y, kC[q].z};
+        double v = 1.0;
+        for (int i = 0; i < 3; ++i)
+            for (int t = 0; t < e[i]; ++t) v *= c[i];
+        return v;
+    };
+    auto rate = [&](const int e[3]) {
+        const int order = e[0] + e[1] + e[2];
+        return order <= 1 ? 1.0 : order == 2 ? p.omega : order == 3 ? p.mrt_omega3 : p.mrt_omega4;
+    };
+    auto relax = [](const double *m, const double *s, int n, double *k) {
+        double mi[100];
+        for (int i = 0; i < n * n; ++i) mi[i] = m[i];
+        invert(mi, n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double v = 0.0;
+                for (int l = 0; l < n; ++l) v += mi[i * n + l] * s[l] * m[l * n + j];
+                k[i * n + j] = v;
+            }
+    };
+    double me[100], se[10], mo[81], so[9];
+    for (int k = 0; k < 10; ++k) {
+        me[k * 10] = mono(even[k], 0);
+        for (int pp = 0; pp < 9; ++pp) me[k * 10 + pp + 1] = 2.0 * mono(even[k], 2 * pp + 1);
+        se[k] = rate(even[k]);
+    }
+    for (int k = 0; k < 9; ++k) {
+        for (int pp = 0; pp < 9; ++pp) mo[k * 9 + pp] = 2.0 * mono(odd[k], 2 * pp + 1);
+        so[k] = rate(odd[k]);
+    }
+    relax(me, se, 10, ke);
+    relax(mo, so, 9, ko);
+}
+
 // Relaxation and force constants of the update in both precisions.
 static void set_coll(lbm_ctx *c) {
     const lbm_params &p = c->p;
@@ -210,6 +296,7 @@ static void set_coll(lbm_ctx *c) {
     d.s = c->scale;
     d.inv_s = 1.0 / c->scale;
     d.compressible = p.compressible;
+    if (p.collision == LBM_MRT) mrt_matrices(p, d.ke, d.ko);
     Coll<float> f = {};
     f.wp = (float)d.wp;
     f.wm = (float)d.wm;
@@ -222,6 +309,8 @@ static void set_coll(lbm_ctx *c) {
     f.s = (float)d.s;
     f.inv_s = (float)d.inv_s;
     f.compressible = d.compressible;
+    for (int i = 0; i < 100; ++i) f.ke[i] = (float)d.ke[i];
+    for (int i = 0; i < 81; ++i) f.ko[i] = (float)d.ko[i];
     c->coll.d = d;
     c->coll.f = f;
 }
@@ -357,13 +446,15 @@ extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
         hipError_t e;
         if (c->p.pattern == LBM_TWO_GRID) {
-            e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->gen, c->coll,
+            e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
+                               c->p.collision == LBM_MRT, c->gen, c->coll,
                                c->buf[c->cur], c->buf[1 - c->cur], c->stream);
             if (e == hipSuccess) c->cur ^= 1;
         } else {
             // even step count: the state is in local layout, so the next step
             // is a neighbour step; odd: a local step.
-            e = launch_step_aa(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->gen, (c->t & 1) == 0,
+            e = launch_step_aa(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
+                               c->p.collision == LBM_MRT, c->gen, (c->t & 1) == 0,
                                c->coll, c->buf[0], c->stream);
         }
         if (e != hipSuccess) return hip_fail(c, e, "step");
@@ -375,7 +466,8 @@ extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
 extern "C" int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst) {
     if (!c) return LBM_EINVAL;
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct buffers");
-    hipError_t e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->gen, c->coll, src, dst,
+    hipError_t e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
+                               c->p.collision == LBM_MRT, c->gen, c->coll, src, dst,
                                   c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "stream_collide");
     return LBM_OK;
@@ -461,8 +553,9 @@ extern "C" int lbm_set_rates(lbm_ctx *c, double omega, const double *accel) {
 extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next,
                                 void *lam_prev, double *grad) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3)
-        return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19 with the second-order equilibria");
+    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3 || c->p.collision == LBM_MRT)
+        return fail(c, LBM_ESTATE,
+                    "the adjoint is written for D3Q19 SRT/TRT with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
     if (!state_t || !lam_next || !lam_prev || lam_next == lam_prev)
@@ -475,8 +568,9 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam
 
 extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *out, void *lam) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3)
-        return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19 with the second-order equilibria");
+    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3 || c->p.collision == LBM_MRT)
+        return fail(c, LBM_ESTATE,
+                    "the adjoint is written for D3Q19 SRT/TRT with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "objectives are defined for the incompressible form only");
     if (kind != LBM_OBJ_KINETIC_ENERGY && kind != LBM_OBJ_OUTLET_FLUX)
@@ -490,8 +584,9 @@ extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *ou
 
 extern "C" int lbm_init_vjp(lbm_ctx *c, const double *u_init, const void *lam0, double *grad_u) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3)
-        return fail(c, LBM_ESTATE, "the adjoint is written for D3Q19 with the second-order equilibria");
+    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3 || c->p.collision == LBM_MRT)
+        return fail(c, LBM_ESTATE,
+                    "the adjoint is written for D3Q19 SRT/TRT with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
     if (!u_init || !lam0 || !grad_u) return fail(c, LBM_EINVAL, "u_init, lam0, grad_u must be set");

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_init_maxdev(Geom g, int compressible
 // ---------------------------------------------------------------------------
 // Two-grid pull step: dst[q][x] = f*_q(x) from src.
 // ---------------------------------------------------------------------------
-template <int QN, int DT, int EQ, bool GEN>
+template <int QN, int DT, int EQ, bool GEN, bool MRT>
 __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<DT>::R> P,
                                                     const typename Store<DT>::T *__restrict__ src,
                                                     typename Store<DT>::T *__restrict__ dst) {
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
         const typename S::T *p = src + (fl ? q : opp(q)) * g.qstride;
         d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_fwd(kC[q].x));
     }
-    collide<R, EQ, QN>(d, P);
+    collide<R, EQ, QN, MRT>(d, P);
 #pragma unroll
     for (int q = 0; q < QN; ++q) S::store(dst + q * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
 }
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
 // Every slot a cell reads is written by the same cell, so the in-place
 // update is race-free.
 // ---------------------------------------------------------------------------
-template <int QN, int DT, int EQ, bool GEN>
+template <int QN, int DT, int EQ, bool GEN, bool MRT>
 __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Store<DT>::R> P,
                                                        typename Store<DT>::T *A) {
     using S = Store<DT>;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
         const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
         d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_fwd(kC[q].x));
     }
-    collide<R, EQ, QN>(d, P);
+    collide<R, EQ, QN, MRT>(d, P);
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
         bool fl;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
     }
 }
 
-template <int QN, int DT, int EQ, bool GEN>
+template <int QN, int DT, int EQ, bool GEN, bool MRT>
 __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename Store<DT>::R> P,
                                                         typename Store<DT>::T *A) {
     using S = Store<DT>;
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename St
     R d[QN];
 #pragma unroll
     for (int q = 0; q < QN; ++q) d[q] = S::load(A + q * g.qstride, idx, (R)wq(QN, q), P.inv_s);
-    collide<R, EQ, QN>(d, P);
+    collide<R, EQ, QN, MRT>(d, P);
 #pragma unroll
     for (int q = 0; q < QN; ++q)
         S::store(A + opp(q) * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
@@ -420,6 +420,11 @@ const Coll<float> &pick<LBM_BF16_SHIFTED>(const CollBoth &P) { return P.f; }
     else if (eq == LBM_EQ_IMPROVED3) { constexpr int QN = 19; constexpr int EQ = LBM_EQ_IMPROVED3; BODY; } \
     else { constexpr int QN = 19; constexpr int EQ = LBM_EQ_STANDARD; BODY; }
 
+// MRT exists for D3Q19 only.
+#define LBM_DISPATCH_MRT(BODY)                                          \
+    if (QN == 19 && mrt) { constexpr bool MRT = true; BODY; }           \
+    else { constexpr bool MRT = false; BODY; }
+
 #define LBM_DISPATCH_Q(BODY)                              \
     if (qn == 27) { constexpr int QN = 27; BODY; }        \
     else { constexpr int QN = 19; BODY; }
@@ -452,29 +457,29 @@ hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, c
     return launch_finalize(sc, cell_blocks(g), 1, 1, sc.result, false, st);
 }
 
-hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool gen, const CollBoth &P,
-                          const void *src, void *dst, hipStream_t st) {
+hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
+                          const CollBoth &P, const void *src, void *dst, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, {
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT({
         using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
-                           (const T *)src, (T *)dst);
-    })));
+        hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN, MRT>), grid, block, 0, st, g,
+                           pick<DT>(P), (const T *)src, (T *)dst);
+    }))));
     return hipGetLastError();
 }
 
-hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool gen, bool neighbor,
-                          const CollBoth &P, void *A, hipStream_t st) {
+hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
+                          bool neighbor, const CollBoth &P, void *A, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, {
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT({
         using T = typename Store<DT>::T;
         if (neighbor)
-            hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
-                               (T *)A);
+            hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN, MRT>), grid, block, 0, st, g,
+                               pick<DT>(P), (T *)A);
         else
-            hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN>), grid, block, 0, st, g, pick<DT>(P),
-                               (T *)A);
-    })));
+            hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN, MRT>), grid, block, 0, st, g,
+                               pick<DT>(P), (T *)A);
+    }))));
     return hipGetLastError();
 }
 

@@ -300,6 +300,10 @@ struct Coll {
     R kappa;        // d omega_minus / d omega (1 for SRT)
     R s, inv_s;     // storage scale
     int compressible;
+    // MRT (D3Q19): relaxation matrices K = M^-1 S M of the even part
+    // [rest, 9 pair sums] and the odd part [9 pair differences], row-major.
+    R ke[100];
+    R ko[81];
 };
 
 // Moments of shifted PDFs: drho = sum d, j = sum c d.
@@ -392,8 +396,11 @@ struct Poly {
     }
 };
 
-// Stream-collide of one cell in shifted variables, in place on d.
-template <typename R, int EQ, int QN = 19>
+// Stream-collide of one cell in shifted variables, in place on d.  With MRT
+// (Sec. 3.2, C = -M^-1 S (M f - m_eq)) the even and odd non-equilibrium
+// vectors are relaxed with the matrices K_e, K_o instead of the scalars
+// omega, omega_minus; the force enters as (I - K_o/2) F.
+template <typename R, int EQ, int QN = 19, bool MRT = false>
 __device__ __forceinline__ void collide(R (&d)[QN], const Coll<R> &P) {
     constexpr int NP = (QN - 1) / 2;
     R drho, jx, jy, jz;
@@ -415,6 +422,40 @@ __device__ __forceinline__ void collide(R (&d)[QN], const Coll<R> &P) {
         for (int p = 0; p < 9; ++p) O[p] += O3[p];
     }
     const R w0 = R(wq(QN, 0));
+    if constexpr (MRT && QN == 19) {
+        R ne[10], no[9];
+        ne[0] = d[0] - w0 * (drho + rho0 * E0);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const int q = 2 * p + 1;
+            const R w = R(wq(QN, q));
+            ne[p + 1] = R(0.5) * (d[q] + d[q + 1]) - w * (drho + rho0 * E[p]);
+            no[p] = R(0.5) * (d[q] - d[q + 1]) - w * rho0 * O[p] + R(0.5) * P.fraw[p];
+        }
+        R te[10], to[9];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            R v = R(0);
+#pragma unroll
+            for (int j = 0; j < 10; ++j) v += P.ke[10 * i + j] * ne[j];
+            te[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            R v = R(0);
+#pragma unroll
+            for (int j = 0; j < 9; ++j) v += P.ko[9 * i + j] * no[j];
+            to[i] = v - P.fraw[i];
+        }
+        d[0] = d[0] - te[0];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const int q = 2 * p + 1;
+            d[q] = d[q] - te[p + 1] - to[p];
+            d[q + 1] = d[q + 1] - te[p + 1] + to[p];
+        }
+        return;
+    }
     d[0] = d[0] - P.wp * (d[0] - w0 * (drho + rho0 * E0));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {

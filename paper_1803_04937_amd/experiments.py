@@ -39,19 +39,22 @@ K_CENTRE = _square_duct_centre_constant()
 
 def duct_spurious_current(D: int, lam2: float, equilibrium: str, dtype: str = "f64",
                           re: float = 10.0, sweeps: float = 3.0, stencil: int = 19,
-                          device=None) -> dict:
+                          mrt=None, device=None) -> dict:
     """Steady-state max |u_y| / max u_x of the duct for one resolution D,
     one Lambda^2 and one equilibrium ("standard" or "improved"; D3Q27 has a
-    single equilibrium)."""
+    single equilibrium).  SRT, or with mrt = (omega3, omega4) the MRT
+    collision whose second-order moments relax at the same omega."""
     import lbm_inputs
     lam = math.sqrt(lam2)
     omega = 1.0 / (lam + 0.5)
     nu = lam / 3.0
     a = re * nu * nu / (K_CENTRE * (D / 2.0) ** 2 * D)
     u0 = torch.as_tensor(lbm_inputs.duct_poiseuille(1, D, D, a, nu))
-    lat = Lattice(1, D, D, u=u0, periodic=(1, 0, 0), equilibrium=equilibrium, collision="srt",
-                  dtype=dtype, omega=omega, accel=(a, 0.0, 0.0), stencil=stencil,
-                  device=device)
+    coll = dict(collision="srt")
+    if mrt is not None:
+        coll = dict(collision="mrt", mrt_omega3=mrt[0], mrt_omega4=mrt[1])
+    lat = Lattice(1, D, D, u=u0, periodic=(1, 0, 0), equilibrium=equilibrium, dtype=dtype,
+                  omega=omega, accel=(a, 0.0, 0.0), stencil=stencil, device=device, **coll)
     steps = int(math.ceil(sweeps * D * D / nu))
     chunks = 10
     per = max(1, steps // chunks)
@@ -66,6 +69,7 @@ def duct_spurious_current(D: int, lam2: float, equilibrium: str, dtype: str = "f
     last, prev = history[-1], history[-2]
     return {"D": D, "lambda2": lam2, "omega": omega, "stencil": stencil,
             "equilibrium": equilibrium if stencil == 19 else "d3q27", "dtype": dtype,
+            "collision": "srt" if mrt is None else f"mrt{tuple(mrt)}",
             "steps": per * chunks, "ratio": last, "ux_max": ux,
             "last_chunk_rel_change": abs(last - prev) / max(abs(last), 1e-300)}
 

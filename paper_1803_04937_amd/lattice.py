@@ -12,7 +12,7 @@ from .capi import LBMError
 
 EQUILIBRIA = {"standard": capi.LBM_EQ_STANDARD, "improved": capi.LBM_EQ_IMPROVED,
               "improved3": capi.LBM_EQ_IMPROVED3}
-COLLISIONS = {"srt": capi.LBM_SRT, "trt": capi.LBM_TRT}
+COLLISIONS = {"srt": capi.LBM_SRT, "trt": capi.LBM_TRT, "mrt": capi.LBM_MRT}
 DTYPES = {"f64": capi.LBM_F64, "f32": capi.LBM_F32, "f32s": capi.LBM_F32_SHIFTED,
           "f16s": capi.LBM_F16_SHIFTED, "bf16s": capi.LBM_BF16_SHIFTED}
 PATTERNS = {"two_grid": capi.LBM_TWO_GRID, "aa": capi.LBM_AA}
@@ -43,13 +43,15 @@ class Lattice:
     def __init__(self, nx, ny, nz, *, u, rho=None, solid=None, periodic=(1, 1, 1),
                  equilibrium="improved", collision="srt", dtype="f32", pattern="two_grid",
                  compressible=False, omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0),
-                 scale=0.0, stencil=19, device=None, stream=None):
+                 scale=0.0, stencil=19, mrt_omega3=1.0, mrt_omega4=1.0, device=None,
+                 stream=None):
         self.device = require_gpu(device)
         self.params = capi.make_params(
             nx, ny, nz, periodic=periodic, equilibrium=_code(EQUILIBRIA, equilibrium),
             collision=_code(COLLISIONS, collision), dtype=_code(DTYPES, dtype),
             pattern=_code(PATTERNS, pattern), compressible=int(bool(compressible)), omega=omega,
-            trt_magic=trt_magic, accel=accel, scale=scale, stencil=stencil)
+            trt_magic=trt_magic, accel=accel, scale=scale, stencil=stencil,
+            mrt_omega3=mrt_omega3, mrt_omega4=mrt_omega4)
         rc, why = capi.lbm_validate(self.params)
         if rc != capi.LBM_OK:
             raise LBMError(rc, why)

@@ -38,8 +38,9 @@ def host(t):
 
 
 def case(nx, ny, nz, periodic=(1, 1, 1), improved=True, trt=False, omega=1.2, magic=3 / 16,
-         accel=(0.0, 0.0, 0.0), solid=None, compressible=False, stencil=19):
-    """(oracle.Config, Lattice keyword arguments) of one case."""
+         accel=(0.0, 0.0, 0.0), solid=None, compressible=False, stencil=19, mrt=None):
+    """(oracle.Config, Lattice keyword arguments) of one case.  mrt: None or
+    the MRT rates (omega3, omega4) of the third- and fourth-order moments."""
     cfg = oracle.Config(nx, ny, nz, periodic=tuple(periodic), improved=improved, trt=trt,
                         compressible=compressible, omega=omega, magic=magic, accel=tuple(accel),
                         solid=solid, stencil=stencil)
@@ -47,6 +48,11 @@ def case(nx, ny, nz, periodic=(1, 1, 1), improved=True, trt=False, omega=1.2, ma
     kw = dict(periodic=tuple(periodic), equilibrium=eq_name,
               collision="trt" if trt else "srt", compressible=compressible, omega=omega,
               trt_magic=magic, accel=tuple(accel), stencil=stencil)
+    if mrt is not None:
+        cfg = oracle.Config(nx, ny, nz, periodic=tuple(periodic), improved=improved,
+                            compressible=compressible, omega=omega, accel=tuple(accel),
+                            solid=solid, mrt=True, omega3=mrt[0], omega4=mrt[1])
+        kw.update(collision="mrt", mrt_omega3=mrt[0], mrt_omega4=mrt[1])
     if solid is not None:
         kw["solid"] = dev(solid, torch.uint8)
     return cfg, kw

@@ -80,6 +80,10 @@ BAD = [
     (dict(dtype=1, adjoint_dtype=0), "adjoint_dtype"),
     (dict(dtype=3, scale=3.0), "power of two"),
     (dict(stencil=15), "stencil"),
+    (dict(collision=2, stencil=27), "MRT"),
+    (dict(collision=2, mrt_omega3=0.0), "mrt_omega3"),
+    (dict(collision=2, mrt_omega4=2.5), "mrt_omega4"),
+    (dict(collision=3), "collision"),
 ]
 
 

@@ -1,0 +1,102 @@
+"""GPU parity of the MRT collision (Sec. 3.2: relaxation in the space of the
+19 kept monomial moments, equilibrium moments from the chosen equilibrium,
+rates omega / omega3 / omega4 for the second-, third- and fourth-order
+moments) against the oracle, which evaluates C = -M^-1 S (M f - m_eq) +
+M^-1 (I - S/2) M F with the full 19 x 19 moment matrix."""
+import numpy as np
+import pytest
+
+import lbm_inputs
+import oracle
+from _helpers import assert_f64_parity, case, host, lattice, random_blobs, reduced_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("improved", [0, 1, 2])
+@pytest.mark.parametrize("pattern", ["two_grid", "aa"])
+def test_mrt_walls_obstacles_force_fp64(improved, pattern):
+    solid = random_blobs((15, 19, 37), seed=90)
+    cfg, kw = case(37, 19, 15, periodic=(1, 0, 0), improved=improved, omega=1.6,
+                   accel=(2e-4, -1e-4, 5e-5), solid=solid, mrt=(1.85, 0.7))
+    u0 = np.random.default_rng(91).uniform(-0.06, 0.06, size=(3,) + cfg.shape)
+    lat = lattice(cfg, kw, u0, pattern=pattern)
+    f = oracle.init(cfg, u0)
+    for n in (1, 10, 1):
+        lat.step(n)
+        f = oracle.step(cfg, f, n)
+        assert_f64_parity(host(lat.get_pdfs()), f, f"{n}")
+
+
+def test_mrt_taylor_green_fp64_many_steps():
+    u0 = lbm_inputs.taylor_green(32, 0.08)
+    cfg, kw = case(32, 32, 32, improved=1, omega=1.25, mrt=(1.1, 1.9))
+    lat = lattice(cfg, kw, u0, pattern="aa")
+    f = oracle.init(cfg, u0)
+    lat.step(40)
+    assert_f64_parity(host(lat.get_pdfs()), oracle.step(cfg, f, 40), "40")
+
+
+def test_mrt_compressible_fp64():
+    cfg, kw = case(17, 13, 11, periodic=(1, 1, 0), improved=1, omega=1.1, accel=(1e-4, 0, 0),
+                   compressible=True, mrt=(1.5, 1.2))
+    rng = np.random.default_rng(92)
+    u0 = rng.uniform(-0.05, 0.05, size=(3,) + cfg.shape)
+    rho0 = 1.0 + 0.05 * rng.standard_normal(cfg.shape)
+    lat = lattice(cfg, kw, u0, rho=rho0)
+    lat.step(5)
+    assert_f64_parity(host(lat.get_pdfs()), oracle.step(cfg, oracle.init(cfg, u0, rho=rho0), 5))
+
+
+def test_mrt_special_rates_reproduce_srt_and_trt_on_the_gpu():
+    """Equal rates give SRT; (omega3, omega4) = (omega_minus, omega) gives TRT."""
+    w, lam = 1.4, 3 / 16
+    wm = 1 / (0.5 + lam / (1 / w - 0.5))
+    base = dict(periodic=(1, 0, 1), improved=1, omega=w, accel=(2e-4, -1e-4, 5e-5),
+                solid=random_blobs((12, 16, 20), seed=93))
+    u0 = np.random.default_rng(94).uniform(-0.06, 0.06, size=(3, 12, 16, 20))
+    out = {}
+    for name, extra in (("srt", {}), ("mrt_srt", dict(mrt=(w, w))),
+                        ("trt", dict(trt=True, magic=lam)), ("mrt_trt", dict(mrt=(wm, w)))):
+        cfg, kw = case(20, 16, 12, **base, **extra)
+        lat = lattice(cfg, kw, u0)
+        lat.step(6)
+        out[name] = host(lat.get_pdfs())
+    assert_f64_parity(out["mrt_srt"], out["srt"], "equal rates")
+    assert_f64_parity(out["mrt_trt"], out["trt"], "TRT rates")
+    assert np.abs(out["srt"] - out["trt"]).max() > 1e-8
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f32s", "f16s", "bf16s"])
+def test_mrt_reduced_precision_one_step(dtype):
+    cfg, kw = case(64, 24, 20, periodic=(1, 0, 1), improved=1, omega=1.95,
+                   accel=(2e-6, 0, 0), solid=random_blobs((20, 24, 64), seed=95),
+                   mrt=(1.6, 1.2))
+    lat = lattice(cfg, kw, lbm_inputs.shear_waves(cfg.shape, seed=96, amax=0.08), dtype=dtype)
+    lat.step(2)
+    f_in = host(lat.get_pdfs())
+    lat.step(1)
+    want = oracle.step(cfg, f_in, 1)
+    ratio = np.abs(host(lat.get_pdfs()) - want) / reduced_bound(want, dtype, lat.scale)
+    assert ratio.max() <= 1.0, ratio.max()
+
+
+def test_mrt_has_no_adjoint_and_needs_d3q19():
+    from paper_1803_04937_amd import LBMError, capi
+    cfg, kw = case(8, 8, 8, improved=1, mrt=(1.2, 1.2))
+    lat = lattice(cfg, kw, np.zeros((3,) + cfg.shape), dtype="f32")
+    lam = lat.new_adjoint()
+    with pytest.raises(LBMError) as e:
+        lat.adjoint_step(lat.state, lam, lat.new_adjoint())
+    assert e.value.status == capi.LBM_ESTATE
+    lat.close()
+
+
+@pytest.mark.parametrize("mrt", [(1.7, 0.8), (0.6, 1.5)])
+def test_mrt_duct_invariant_on_the_gpu(mrt):
+    """Sec. 3.3: with Maxwellian equilibrium moments (D3Q19-I) the MRT duct
+    keeps u_y = u_z = 0 for any free rates; the standard moments do not."""
+    from paper_1803_04937_amd.experiments import duct_spurious_current
+    imp = duct_spurious_current(25, 4 / 25, "improved", mrt=mrt)
+    std = duct_spurious_current(25, 4 / 25, "standard", mrt=mrt)
+    assert imp["ratio"] < 1e-13 and std["ratio"] > 1e-6, (imp, std)

@@ -125,7 +125,7 @@ def main():
         ln, lp = (lam[0], lam[1]) if i % 2 == 0 else (lam[1], lam[0])
         if ev is not None:
             ev[0].record()
-        lat.stream_collide(src, dst)
+        lat.stream_collide(src, dst, i)
         if ev is not None:
             ev[1].record()
         lat.adjoint_step(src, ln, lp, grad)
@@ -193,7 +193,9 @@ def main():
                          ("fwd_f16s_I_trt", dict(dtype="f16s")),
                          ("fwd_bf16s_I_trt", dict(dtype="bf16s")),
                          ("fwd_f32_I_trt_aa", dict(dtype="f32", pattern="aa")),
-                         ("fwd_f16s_I_trt_aa", dict(dtype="f16s", pattern="aa"))]:
+                         ("fwd_f16s_I_trt_aa", dict(dtype="f16s", pattern="aa")),
+                         ("fwd_f16s_I_trt_stochastic",
+                          dict(dtype="f16s", rounding="stochastic", seed=1))]:
             _log(f"extra {name}")
             c = dict(common)
             lat2 = Lattice(n, n, n, u=u0, **c, **kw)

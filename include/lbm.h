@@ -94,6 +94,19 @@ enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2 };
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2, LBM_F16_SHIFTED = 3,
        LBM_BF16_SHIFTED = 4 };
 
+/* Rounding of the 16-bit stores s (f - w) (a6).  NEAREST: round to nearest
+ * even.  STOCHASTIC: the FP32 value plus uniform random bits below the kept
+ * mantissa, truncated toward zero, so the stored value is the lower or upper
+ * neighbour with probabilities that make its expectation exact (FP16: below
+ * 2^-14 s, its subnormal range, the last step is round to nearest).  The
+ * random bits of f*_q(x) at step t are a counter-based hash of (seed, t, x,
+ * q): runs are reproducible and both patterns store identical values.  With
+ * round to nearest, a per-step change smaller than half a storage ulp of
+ * s (f - w) is lost every step, which stalls a flow driven by a small body
+ * force; stochastic rounding keeps it on average.  Ignored by the FP64 and
+ * FP32 formats; the initial state and lbm_set_pdfs round to nearest. */
+enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
+
 /* Streaming patterns.  TWO_GRID: pull from one buffer into another.  AA:
  * one buffer updated in place, alternating a step that reads and writes the
  * cell's own slots with a step that reads and writes the neighbours'. */
@@ -122,6 +135,8 @@ typedef struct {
                                  lbm_init from the initial state                  */
     double mrt_omega3;        /* MRT rate of the third-order moments, (0, 2)      */
     double mrt_omega4;        /* MRT rate of the fourth-order moments, (0, 2)     */
+    int32_t rounding;         /* LBM_ROUND_NEAREST / LBM_ROUND_STOCHASTIC          */
+    uint32_t seed;            /* key of the stochastic rounding                    */
 } lbm_params;
 
 /* Library version string. */
@@ -171,8 +186,11 @@ int lbm_step(lbm_ctx *c, int64_t nsteps);
 /* One two-grid step from src into dst (state buffers of this context's dtype
  * in the two-grid layout, src != dst), leaving the context's own state
  * untouched.  Used to recompute trajectories for the adjoint; allowed for
- * contexts of either pattern. */
-int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst);
+ * contexts of either pattern.  t >= 0 is the time of the state in src: the
+ * step is the one lbm_step performs from time t, so with stochastic rounding
+ * the result equals lbm_step's bit for bit.  LBM_EINVAL if src == dst or a
+ * pointer is NULL or t < 0. */
+int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst, int64_t t);
 
 /* Device pointer of the buffer that holds the current state. */
 void *lbm_current_state(lbm_ctx *c);

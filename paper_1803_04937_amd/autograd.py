@@ -40,6 +40,8 @@ class RolloutConfig:
     checkpoint_every: int | None = None
     solid: torch.Tensor | None = field(default=None, repr=False)
     scale: float = 0.0
+    rounding: str = "nearest"
+    seed: int = 0
 
     @property
     def segment(self) -> int:
@@ -56,7 +58,7 @@ class _Rollout(torch.autograd.Function):
                       equilibrium=cfg.equilibrium, collision=cfg.collision, dtype=cfg.dtype,
                       omega=float(omega), trt_magic=cfg.trt_magic,
                       accel=tuple(float(v) for v in accel.detach().cpu()), scale=cfg.scale,
-                      device=u_init.device)
+                      rounding=cfg.rounding, seed=cfg.seed, device=u_init.device)
         C = cfg.segment
         ckpts = {}
         for t in range(cfg.steps):
@@ -86,7 +88,7 @@ class _Rollout(torch.autograd.Function):
             end = min(start + C, T)
             ring[0] = ctx.ckpts[start]
             for k in range(1, end - start):
-                lat.stream_collide(ring[k - 1], ring[k])
+                lat.stream_collide(ring[k - 1], ring[k], start + k - 1)
             for t in reversed(range(start, end)):
                 lat.adjoint_step(ring[t - start], lam_next, lam_prev, grad)
                 lam_next, lam_prev = lam_prev, lam_next

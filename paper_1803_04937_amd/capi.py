@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_EQ_STANDARD, LBM_EQ_IMPROVED, LBM_EQ_IMPROVED3 = 0, 1, 2
 LBM_SRT, LBM_TRT, LBM_MRT = 0, 1, 2
+LBM_ROUND_NEAREST, LBM_ROUND_STOCHASTIC = 0, 1
 LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3, 4
 LBM_TWO_GRID, LBM_AA = 0, 1
 LBM_OBJ_KINETIC_ENERGY, LBM_OBJ_OUTLET_FLUX = 0, 1
@@ -51,6 +52,7 @@ class lbm_params(ctypes.Structure):
         ("omega", ctypes.c_double), ("trt_magic", ctypes.c_double),
         ("accel", ctypes.c_double * 3), ("scale", ctypes.c_double),
         ("mrt_omega3", ctypes.c_double), ("mrt_omega4", ctypes.c_double),
+        ("rounding", ctypes.c_int32), ("seed", ctypes.c_uint32),
     ]
 
 
@@ -73,7 +75,7 @@ def _load():
         "lbm_destroy": ([P], None),
         "lbm_last_error": ([P], ctypes.c_char_p),
         "lbm_step": ([P, ctypes.c_int64], ctypes.c_int),
-        "lbm_stream_collide": ([P, P, P], ctypes.c_int),
+        "lbm_stream_collide": ([P, P, P, ctypes.c_int64], ctypes.c_int),
         "lbm_current_state": ([P], P),
         "lbm_copy_state": ([P, P, P], ctypes.c_int),
         "lbm_time": ([P], ctypes.c_int64),
@@ -120,7 +122,8 @@ def _check(rc: int, ctx=None):
 def make_params(nx, ny, nz, periodic=(1, 1, 1), equilibrium=LBM_EQ_IMPROVED, collision=LBM_SRT,
                 dtype=LBM_F32, pattern=LBM_TWO_GRID, compressible=0, adjoint_dtype=None,
                 omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0), scale=0.0,
-                stencil=19, mrt_omega3=1.0, mrt_omega4=1.0) -> lbm_params:
+                stencil=19, mrt_omega3=1.0, mrt_omega4=1.0, rounding=0,
+                seed=0) -> lbm_params:
     p = lbm_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     for d in range(3):
@@ -140,6 +143,8 @@ def make_params(nx, ny, nz, periodic=(1, 1, 1), equilibrium=LBM_EQ_IMPROVED, col
     p.scale = float(scale)
     p.mrt_omega3 = float(mrt_omega3)
     p.mrt_omega4 = float(mrt_omega4)
+    p.rounding = int(rounding)
+    p.seed = int(seed) & 0xFFFFFFFF
     return p
 
 
@@ -206,8 +211,8 @@ def lbm_step(ctx, nsteps: int) -> None:
     _check(_lib.lbm_step(ctx, int(nsteps)), ctx)
 
 
-def lbm_stream_collide(ctx, src, dst) -> None:
-    _check(_lib.lbm_stream_collide(ctx, _addr(src), _addr(dst)), ctx)
+def lbm_stream_collide(ctx, src, dst, t) -> None:
+    _check(_lib.lbm_stream_collide(ctx, _addr(src), _addr(dst), int(t)), ctx)
 
 
 def lbm_current_state(ctx) -> int:

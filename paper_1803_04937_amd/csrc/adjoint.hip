@@ -25,7 +25,7 @@ struct Lam<LBM_F32> {
 // exactly one cell in the forward step, so each lam_t slot is written
 // exactly once.  Solid cells copy lam through.
 template <int DT, int LT, int EQ, bool GEN, bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_adjoint(
+__global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     Geom g, Coll<typename Store<DT>::R> P, const typename Store<DT>::T *__restrict__ state,
     const typename Lam<LT>::T *__restrict__ lam_next, typename Lam<LT>::T *__restrict__ lam_prev,
     double *partials) {

@@ -143,6 +143,10 @@ static int validate(const lbm_params *p, std::string &why) {
             why = "accel must be finite";
             return LBM_EINVAL;
         }
+    if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC) {
+        why = "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC";
+        return LBM_EINVAL;
+    }
     const bool q16 = p->dtype == LBM_F16_SHIFTED || p->dtype == LBM_BF16_SHIFTED;
     if (q16 && p->scale != 0.0 && !is_pow2(p->scale)) {
         why = "scale must be 0 or a positive power of two";
@@ -315,6 +319,12 @@ static void set_coll(lbm_ctx *c) {
     c->coll.f = f;
 }
 
+// Stochastic rounding applies to the 16-bit formats only.
+static bool sr(const lbm_ctx *c) {
+    return c->p.rounding == LBM_ROUND_STOCHASTIC &&
+           (c->p.dtype == LBM_F16_SHIFTED || c->p.dtype == LBM_BF16_SHIFTED);
+}
+
 static Layout layout_of(const lbm_ctx *c) {
     if (c->p.pattern == LBM_TWO_GRID) return kDirect;
     return (c->t & 1) ? kAANeighbor : kAALocal;
@@ -447,15 +457,15 @@ extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
         hipError_t e;
         if (c->p.pattern == LBM_TWO_GRID) {
             e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                               c->p.collision == LBM_MRT, c->gen, c->coll,
-                               c->buf[c->cur], c->buf[1 - c->cur], c->stream);
+                               c->p.collision == LBM_MRT, c->gen, sr(c), step_key(c->p.seed, c->t),
+                               c->coll, c->buf[c->cur], c->buf[1 - c->cur], c->stream);
             if (e == hipSuccess) c->cur ^= 1;
         } else {
             // even step count: the state is in local layout, so the next step
             // is a neighbour step; odd: a local step.
             e = launch_step_aa(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                               c->p.collision == LBM_MRT, c->gen, (c->t & 1) == 0,
-                               c->coll, c->buf[0], c->stream);
+                               c->p.collision == LBM_MRT, c->gen, sr(c), step_key(c->p.seed, c->t),
+                               (c->t & 1) == 0, c->coll, c->buf[0], c->stream);
         }
         if (e != hipSuccess) return hip_fail(c, e, "step");
         c->t += 1;
@@ -463,12 +473,13 @@ extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
     return LBM_OK;
 }
 
-extern "C" int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst) {
+extern "C" int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst, int64_t t) {
     if (!c) return LBM_EINVAL;
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct buffers");
+    if (t < 0) return fail(c, LBM_EINVAL, "t must be >= 0");
     hipError_t e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                               c->p.collision == LBM_MRT, c->gen, c->coll, src, dst,
-                                  c->stream);
+                                  c->p.collision == LBM_MRT, c->gen, sr(c), step_key(c->p.seed, t),
+                                  c->coll, src, dst, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "stream_collide");
     return LBM_OK;
 }

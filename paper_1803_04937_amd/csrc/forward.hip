@@ -122,10 +122,11 @@ __global__ __launch_bounds__(kBlock) void k_init_maxdev(Geom g, int compressible
 // ---------------------------------------------------------------------------
 // Two-grid pull step: dst[q][x] = f*_q(x) from src.
 // ---------------------------------------------------------------------------
-template <int QN, int DT, int EQ, bool GEN, bool MRT>
+template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR>
 __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<DT>::R> P,
                                                     const typename Store<DT>::T *__restrict__ src,
-                                                    typename Store<DT>::T *__restrict__ dst) {
+                                                    typename Store<DT>::T *__restrict__ dst,
+                                                    uint32_t key) {
     using S = Store<DT>;
     using R = typename S::R;
     const uint32_t idx = cell_index();
@@ -141,8 +142,14 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
         d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_fwd(kC[q].x));
     }
     collide<R, EQ, QN, MRT>(d, P);
+    SrBits rb{SR ? mix32(idx ^ key) : 0u};
 #pragma unroll
-    for (int q = 0; q < QN; ++q) S::store(dst + q * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
+    for (int q = 0; q < QN; ++q) {
+        if constexpr (SR)
+            store_sr<DT>(dst + q * g.qstride, idx, d[q], P.s, rb.next(q));
+        else
+            S::store(dst + q * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -154,9 +161,9 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
 // Every slot a cell reads is written by the same cell, so the in-place
 // update is race-free.
 // ---------------------------------------------------------------------------
-template <int QN, int DT, int EQ, bool GEN, bool MRT>
+template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR>
 __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Store<DT>::R> P,
-                                                       typename Store<DT>::T *A) {
+                                                       typename Store<DT>::T *A, uint32_t key) {
     using S = Store<DT>;
     using R = typename S::R;
     const uint32_t idx = cell_index();
@@ -172,18 +179,22 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
         d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_fwd(kC[q].x));
     }
     collide<R, EQ, QN, MRT>(d, P);
+    SrBits rb{SR ? mix32(idx ^ key) : 0u};
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, +1, fl);
         typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
-        S::store(p, fl ? c : idx, d[q], (R)wq(QN, q), P.s, nt_store(kC[q].x));
+        if constexpr (SR)
+            store_sr<DT>(p, fl ? c : idx, d[q], P.s, rb.next(q), nt_store(kC[q].x));
+        else
+            S::store(p, fl ? c : idx, d[q], (R)wq(QN, q), P.s, nt_store(kC[q].x));
     }
 }
 
-template <int QN, int DT, int EQ, bool GEN, bool MRT>
+template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR>
 __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename Store<DT>::R> P,
-                                                        typename Store<DT>::T *A) {
+                                                        typename Store<DT>::T *A, uint32_t key) {
     using S = Store<DT>;
     using R = typename S::R;
     const uint32_t idx = cell_index();
@@ -193,9 +204,14 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename St
 #pragma unroll
     for (int q = 0; q < QN; ++q) d[q] = S::load(A + q * g.qstride, idx, (R)wq(QN, q), P.inv_s);
     collide<R, EQ, QN, MRT>(d, P);
+    SrBits rb{SR ? mix32(idx ^ key) : 0u};
 #pragma unroll
-    for (int q = 0; q < QN; ++q)
-        S::store(A + opp(q) * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
+    for (int q = 0; q < QN; ++q) {
+        if constexpr (SR)
+            store_sr<DT>(A + opp(q) * g.qstride, idx, d[q], P.s, rb.next(q));
+        else
+            S::store(A + opp(q) * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -420,6 +436,13 @@ const Coll<float> &pick<LBM_BF16_SHIFTED>(const CollBoth &P) { return P.f; }
     else if (eq == LBM_EQ_IMPROVED3) { constexpr int QN = 19; constexpr int EQ = LBM_EQ_IMPROVED3; BODY; } \
     else { constexpr int QN = 19; constexpr int EQ = LBM_EQ_STANDARD; BODY; }
 
+// Stochastic rounding exists for the 16-bit formats only.
+#define LBM_DISPATCH_SR(BODY)                                                       \
+    if constexpr (DT == LBM_F16_SHIFTED || DT == LBM_BF16_SHIFTED) {                \
+        if (sr) { constexpr bool SR = true; BODY; }                                 \
+        else { constexpr bool SR = false; BODY; }                                   \
+    } else { constexpr bool SR = false; BODY; }
+
 // MRT exists for D3Q19 only.
 #define LBM_DISPATCH_MRT(BODY)                                          \
     if (QN == 19 && mrt) { constexpr bool MRT = true; BODY; }           \
@@ -458,28 +481,30 @@ hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, c
 }
 
 hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
-                          const CollBoth &P, const void *src, void *dst, hipStream_t st) {
+                          bool sr, uint32_t key, const CollBoth &P, const void *src, void *dst,
+                          hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT({
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(LBM_DISPATCH_SR({
         using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN, MRT>), grid, block, 0, st, g,
-                           pick<DT>(P), (const T *)src, (T *)dst);
-    }))));
+        hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN, MRT, SR>), grid, block, LBM_STEP_LDS_BYTES,
+                           st, g, pick<DT>(P), (const T *)src, (T *)dst, key);
+    })))));
     return hipGetLastError();
 }
 
 hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
-                          bool neighbor, const CollBoth &P, void *A, hipStream_t st) {
+                          bool sr, uint32_t key, bool neighbor, const CollBoth &P, void *A,
+                          hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT({
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(LBM_DISPATCH_SR({
         using T = typename Store<DT>::T;
         if (neighbor)
-            hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN, MRT>), grid, block, 0, st, g,
-                               pick<DT>(P), (T *)A);
+            hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN, MRT, SR>), grid, block,
+                               LBM_STEP_LDS_BYTES, st, g, pick<DT>(P), (T *)A, key);
         else
-            hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN, MRT>), grid, block, 0, st, g,
-                               pick<DT>(P), (T *)A);
-    }))));
+            hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN, MRT, SR>), grid, block,
+                               LBM_STEP_LDS_BYTES, st, g, pick<DT>(P), (T *)A, key);
+    })))));
     return hipGetLastError();
 }
 

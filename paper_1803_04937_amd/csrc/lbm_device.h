@@ -64,6 +64,26 @@ __host__ __device__ constexpr double wq(int qn, int q) {
 #ifndef LBM_NT_SHIFTED_STORES
 #define LBM_NT_SHIFTED_STORES 1
 #endif
+// Occupancy (build-time tuning).  LBM_STEP_LDS_BYTES > 0 reserves that much
+// dynamic LDS per stream-collide block, which caps the resident blocks per
+// CU at floor(160 KiB / bytes) (one 256-thread block = one wave per SIMD).
+// The default, 26.5 KiB, allows 6 blocks per CU: measured on MI355X at 256^3,
+// the two-grid pull moves 3 % more bytes per second with 4 to 6 resident
+// blocks than with the 8 its registers allow (FP32 5.57 -> 5.75 TB/s), and
+// falls off at 3; the AA steps do not change.
+// LBM_ADJ_WAVES_PER_EU > 0 asks the compiler to fit the adjoint kernel into
+// that many waves per SIMD (4 instead of its natural 3 was 3.5 % slower).
+#ifndef LBM_STEP_LDS_BYTES
+#define LBM_STEP_LDS_BYTES 27136
+#endif
+#ifndef LBM_ADJ_WAVES_PER_EU
+#define LBM_ADJ_WAVES_PER_EU 0
+#endif
+#if LBM_ADJ_WAVES_PER_EU > 0
+#define LBM_ADJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(LBM_ADJ_WAVES_PER_EU)))
+#else
+#define LBM_ADJ_OCCUPANCY
+#endif
 constexpr bool kNtShiftedLoadsForward = LBM_NT_FWD_SHIFTED_LOADS;
 constexpr bool kNtShiftedLoadsAdjoint = LBM_NT_ADJ_SHIFTED_LOADS;
 constexpr bool kNtShiftedStores = LBM_NT_SHIFTED_STORES;
@@ -174,6 +194,66 @@ struct Store<LBM_BF16_SHIFTED> {
         st(p + i, static_cast<__bf16>(d * s), nt);  // round to nearest even
     }
 };
+
+// ---------------------------------------------------------------------------
+// Stochastic rounding of the 16-bit formats.  The random bits of the value
+// f*_q(x) written by step t are a function of (seed, t, x, q) alone: the same
+// logical population gets the same bits in the two-grid and the AA pattern,
+// and every run is reproducible.  The cell hash mixes (seed, t, x) with the
+// 32-bit finaliser of MurmurHash3 (Appleby), a bijection with full avalanche.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+// Key of step t under a seed (host side, once per launch).
+inline uint32_t step_key(uint32_t seed, int64_t t) {
+    return mix32(seed ^ mix32((uint32_t)t ^ mix32((uint32_t)((uint64_t)t >> 32) + 0x9e3779b9u)));
+}
+
+// 16 random bits per direction of one cell, drawn in direction order from
+// the cell hash: the rest direction takes its high half; each opposite pair
+// (q = 2p+1, 2p+2) advances a xorshift32 generator (Marsaglia 2003, shifts
+// 13, 17, 5) once and takes the low and the high half of the new state.
+// Only shifts and xors, so the per-cell cost is one hash.
+struct SrBits {
+    uint32_t r;
+    __device__ __forceinline__ uint32_t next(int q) {
+        if (q & 1) {
+            r ^= r << 13;
+            r ^= r >> 17;
+            r ^= r << 5;
+            return r & 0xffffu;
+        }
+        return r >> 16;
+    }
+};
+
+// Round v to the format that keeps the top 23 - DROP bits of the FP32
+// mantissa: add DROP uniform random bits below the kept ones and truncate
+// toward zero.  The result is the lower or the upper neighbour with
+// probabilities proportional to the distance from the other, so its
+// expectation is v.  (FP16: DROP = 13 for |v| >= 2^-14, the normal range.)
+template <int DROP>
+__device__ __forceinline__ float sr_truncate(float v, uint32_t r) {
+    constexpr uint32_t mask = (1u << DROP) - 1u;
+    const uint32_t b = (__float_as_uint(v) + (r & mask)) & ~mask;
+    return __uint_as_float(b);
+}
+
+template <int DT>
+__device__ __forceinline__ void store_sr(typename Store<DT>::T *p, uint32_t i, float d, float s,
+                                         uint32_t r, bool nt = true) {
+    if constexpr (DT == LBM_F16_SHIFTED)
+        st(p + i, static_cast<_Float16>(sr_truncate<13>(d * s, r)), nt);
+    else if constexpr (DT == LBM_BF16_SHIFTED)
+        st(p + i, static_cast<__bf16>(sr_truncate<16>(d * s, r)), nt);
+}
 
 // Canonical (FP64) access: f = w + d.  The raw formats override these with
 // exact copies.

@@ -12,7 +12,12 @@ square-duct Poiseuille solution, u_max = K a (D/2)^2 / nu, K = 0.29468...;
 the run starts from that solution and stops after `sweeps` viscous times
 D^2 / nu.
 
+Also here: a flow driven from rest by a small body force in every storage
+type, which measures how the rounding of the stored f - w treats a per-step
+force increment near its half-ulp (`driven_flow`).
+
 Usage: python -m paper_1803_04937_amd.experiments [--dtype f64] [--sizes 15,25,45]
+       python -m paper_1803_04937_amd.experiments --driven-flow
 """
 from __future__ import annotations
 
@@ -83,6 +88,37 @@ def convergence_order(results):
     return sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sum((x - mx) ** 2 for x in xs)
 
 
+def driven_flow(dtype: str, shape=(32, 32, 32), walls: bool = False, g: float = 2e-6,
+                omega: float = 1.95, times=(2000, 20000), rounding: str = "nearest",
+                seed: int = 0, device=None) -> dict:
+    """Flow driven from rest by a small body force g along x (D3Q19-I TRT,
+    Lambda = 3/16), stored in one storage type: the mean u_x over the fluid
+    at each time in `times`.  In a periodic box every cell stays identical and
+    the exact answer is u_x = (t - 1/2) g (the momentum grows by g per step,
+    the read-out subtracts g/2), so the relative deviation measures how much
+    of the per-step force increment, 3 w_q c_q.g, survives the rounding of the
+    stored f - w.  With walls on y and z (a duct) compare with an FP64 run."""
+    nz, ny, nx = shape
+    u0 = torch.zeros((3, nz, ny, nx), dtype=torch.float64)
+    lat = Lattice(nx, ny, nz, u=u0, periodic=(1, 0, 0) if walls else (1, 1, 1),
+                  equilibrium="improved", collision="trt", dtype=dtype, omega=omega,
+                  accel=(g, 0.0, 0.0), rounding=rounding, seed=seed, device=device)
+    rows, done = [], 0
+    for t in times:
+        lat.step(t - done)
+        done = t
+        _, u = lat.moments()
+        ux = u[0].mean().item()
+        row = {"t": t, "mean_ux": ux}
+        if not walls:
+            row["rel_dev"] = ux / ((t - 0.5) * g) - 1.0
+        rows.append(row)
+    scale = lat.scale
+    lat.close()
+    return {"dtype": dtype, "rounding": rounding, "shape": list(shape), "walls": walls, "g": g,
+            "omega": omega, "scale": scale, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dtype", default="f64")
@@ -91,7 +127,22 @@ def main():
     ap.add_argument("--d3q27", action="store_true", help="also run the D3Q27 stencil")
     ap.add_argument("--sweep", type=int, default=0,
                     help="also sweep Lambda^2 at this D for the standard equilibrium")
+    ap.add_argument("--driven-flow", action="store_true",
+                    help="only run the small-force driven flow in every storage type")
     a = ap.parse_args()
+    if a.driven_flow:
+        runs = [(dt, "nearest") for dt in ("f64", "f32", "f32s", "f16s", "bf16s")]
+        runs += [("f16s", "stochastic"), ("bf16s", "stochastic")]
+        for walls in (False, True):
+            ref = None
+            for dt, rnd in runs:
+                r = driven_flow(dt, walls=walls, rounding=rnd)
+                if walls:
+                    ref = ref or r
+                    for row, r64 in zip(r["rows"], ref["rows"]):
+                        row["rel_dev_vs_f64"] = row["mean_ux"] / r64["mean_ux"] - 1.0
+                print(json.dumps(r), flush=True)
+        return
     sizes = [int(v) for v in a.sizes.split(",")]
     out = {}
     for lam2 in [float(v) for v in a.lambda2.split(",")]:

@@ -16,6 +16,7 @@ COLLISIONS = {"srt": capi.LBM_SRT, "trt": capi.LBM_TRT, "mrt": capi.LBM_MRT}
 DTYPES = {"f64": capi.LBM_F64, "f32": capi.LBM_F32, "f32s": capi.LBM_F32_SHIFTED,
           "f16s": capi.LBM_F16_SHIFTED, "bf16s": capi.LBM_BF16_SHIFTED}
 PATTERNS = {"two_grid": capi.LBM_TWO_GRID, "aa": capi.LBM_AA}
+ROUNDINGS = {"nearest": capi.LBM_ROUND_NEAREST, "stochastic": capi.LBM_ROUND_STOCHASTIC}
 STORAGE_TORCH = {capi.LBM_F64: torch.float64, capi.LBM_F32: torch.float32,
                  capi.LBM_F32_SHIFTED: torch.float32, capi.LBM_F16_SHIFTED: torch.float16,
                  capi.LBM_BF16_SHIFTED: torch.bfloat16}
@@ -43,15 +44,16 @@ class Lattice:
     def __init__(self, nx, ny, nz, *, u, rho=None, solid=None, periodic=(1, 1, 1),
                  equilibrium="improved", collision="srt", dtype="f32", pattern="two_grid",
                  compressible=False, omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0),
-                 scale=0.0, stencil=19, mrt_omega3=1.0, mrt_omega4=1.0, device=None,
-                 stream=None):
+                 scale=0.0, stencil=19, mrt_omega3=1.0, mrt_omega4=1.0, rounding="nearest",
+                 seed=0, device=None, stream=None):
         self.device = require_gpu(device)
         self.params = capi.make_params(
             nx, ny, nz, periodic=periodic, equilibrium=_code(EQUILIBRIA, equilibrium),
             collision=_code(COLLISIONS, collision), dtype=_code(DTYPES, dtype),
             pattern=_code(PATTERNS, pattern), compressible=int(bool(compressible)), omega=omega,
             trt_magic=trt_magic, accel=accel, scale=scale, stencil=stencil,
-            mrt_omega3=mrt_omega3, mrt_omega4=mrt_omega4)
+            mrt_omega3=mrt_omega3, mrt_omega4=mrt_omega4,
+            rounding=_code(ROUNDINGS, rounding), seed=seed)
         rc, why = capi.lbm_validate(self.params)
         if rc != capi.LBM_OK:
             raise LBMError(rc, why)
@@ -120,8 +122,9 @@ class Lattice:
     def step(self, n: int = 1) -> None:
         capi.lbm_step(self.ctx, n)
 
-    def stream_collide(self, src: torch.Tensor, dst: torch.Tensor) -> None:
-        capi.lbm_stream_collide(self.ctx, src, dst)
+    def stream_collide(self, src: torch.Tensor, dst: torch.Tensor, t: int = 0) -> None:
+        """One two-grid step from src (the state at time t) into dst."""
+        capi.lbm_stream_collide(self.ctx, src, dst, t)
 
     def copy_state(self, src: torch.Tensor, dst: torch.Tensor) -> None:
         capi.lbm_copy_state(self.ctx, src, dst)

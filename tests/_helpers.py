@@ -6,7 +6,8 @@ Tolerances (per PDF value, f = post-collision PDF, w_q its weight):
   FP64 storage      |f_gpu - f_oracle| <= 1e-12 max(|f_oracle|, w_q)
   reduced storage   one step from the same stored state:
                     |f_gpu - f_oracle| <= half a storage ulp of the stored
-                    quantity (f, or s (f - w) for the shifted formats)
+                    quantity (f, or s (f - w) for the shifted formats; a
+                    whole ulp with stochastic rounding)
                     + an FP32 arithmetic allowance of 2^-18 max(|f - w|, w_q / 8)
                     (about 64 rounding errors of the largest term of the
                     shifted update).
@@ -58,10 +59,10 @@ def case(nx, ny, nz, periodic=(1, 1, 1), improved=True, trt=False, omega=1.2, ma
     return cfg, kw
 
 
-def lattice(cfg, kw, u, rho=None, dtype="f64", pattern="two_grid", scale=0.0):
+def lattice(cfg, kw, u, rho=None, dtype="f64", pattern="two_grid", scale=0.0, **extra):
     from paper_1803_04937_amd import Lattice
     return Lattice(cfg.nx, cfg.ny, cfg.nz, u=dev(u), rho=None if rho is None else dev(rho),
-                   dtype=dtype, pattern=pattern, scale=scale, **kw)
+                   dtype=dtype, pattern=pattern, scale=scale, **kw, **extra)
 
 
 def random_blobs(shape, seed, frac=0.08):
@@ -97,8 +98,10 @@ def ulp_half(x, dtype):
     return 0.5 * 2.0 ** (e - 23)
 
 
-def reduced_bound(f_ref, dtype, scale):
-    """Per-value error bound of one reduced-precision step (see module doc)."""
+def reduced_bound(f_ref, dtype, scale, rounding="nearest"):
+    """Per-value error bound of one reduced-precision step (see module doc).
+    Stochastic rounding of the 16-bit formats may land on either neighbour:
+    a whole ulp instead of half."""
     nq = f_ref.shape[0]
     wq = weights_for(nq).reshape((nq,) + (1,) * (f_ref.ndim - 1))
     d = f_ref - wq
@@ -108,4 +111,5 @@ def reduced_bound(f_ref, dtype, scale):
     if dtype == "f32s":
         return ulp_half(np.abs(d) + arith, "f32") + arith
     s = scale
-    return ulp_half(s * (np.abs(d) + arith), dtype) / s + arith
+    k = 2.0 if rounding == "stochastic" else 1.0
+    return k * ulp_half(s * (np.abs(d) + arith), dtype) / s + arith

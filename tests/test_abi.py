@@ -84,6 +84,7 @@ BAD = [
     (dict(collision=2, mrt_omega3=0.0), "mrt_omega3"),
     (dict(collision=2, mrt_omega4=2.5), "mrt_omega4"),
     (dict(collision=3), "collision"),
+    (dict(rounding=2), "rounding"),
 ]
 
 

@@ -176,7 +176,7 @@ hipError_t launch_adjoint(const Geom &g, int dtype, int ltype, int eq, bool gen,
     const bool want = grad != nullptr;
     if (eq != LBM_EQ_STANDARD && eq != LBM_EQ_IMPROVED) return hipErrorInvalidValue;
 #define LBM_ADJ(DT, LT, EQ, GEN, GRAD, COLL)                                                     \
-    hipLaunchKernelGGL((k_adjoint<DT, LT, EQ, GEN, GRAD>), grid, block, 0, st, g, COLL,          \
+    hipLaunchKernelGGL((k_adjoint<DT, LT, EQ, GEN, GRAD>), grid, block, LBM_ADJ_LDS_BYTES, st, g, COLL,          \
                        (const typename Store<DT>::T *)state, (const typename Lam<LT>::T *)lam_next, \
                        (typename Lam<LT>::T *)lam_prev, sc.partials)
 #define LBM_ADJ_G(DT, LT, COLL)                                                  \

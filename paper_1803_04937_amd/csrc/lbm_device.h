@@ -72,12 +72,17 @@ __host__ __device__ constexpr double wq(int qn, int q) {
 // blocks than with the 8 its registers allow (FP32 5.57 -> 5.75 TB/s), and
 // falls off at 3; the AA steps do not change.
 // LBM_ADJ_WAVES_PER_EU > 0 asks the compiler to fit the adjoint kernel into
-// that many waves per SIMD (4 instead of its natural 3 was 3.5 % slower).
+// that many waves per SIMD, LBM_ADJ_LDS_BYTES caps its resident blocks like
+// LBM_STEP_LDS_BYTES.  Its registers allow 3 blocks per CU; 4 (fitted by the
+// compiler) was 3.5 % slower and 2 was 6 % slower, so neither is set.
 #ifndef LBM_STEP_LDS_BYTES
 #define LBM_STEP_LDS_BYTES 27136
 #endif
 #ifndef LBM_ADJ_WAVES_PER_EU
 #define LBM_ADJ_WAVES_PER_EU 0
+#endif
+#ifndef LBM_ADJ_LDS_BYTES
+#define LBM_ADJ_LDS_BYTES 0
 #endif
 #if LBM_ADJ_WAVES_PER_EU > 0
 #define LBM_ADJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(LBM_ADJ_WAVES_PER_EU)))

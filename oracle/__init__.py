@@ -228,23 +228,22 @@ def moments(cfg: Config, f):
 def adjoint_step(cfg: Config, f_t, lam_next):
     """(lam_prev, grad[4] = [dJ/domega, dJ/da_x, dJ/da_y, dJ/da_z]) of one step."""
     lib = _load()
-    f_t = _f64(f_t, (NQ,) + cfg.shape)
-    lam_next = _f64(lam_next, (NQ,) + cfg.shape)
+    f_t = _f64(f_t, (cfg.q,) + cfg.shape)
+    lam_next = _f64(lam_next, (cfg.q,) + cfg.shape)
     lam_prev = np.empty_like(lam_next)
     grad = np.zeros(4)
     ref, _keep = cfg._c()
     rc = lib.oracle_adjoint_step(ref, _ptr(cfg._solid()), _ptr(f_t), _ptr(lam_next),
                                  _ptr(lam_prev), _ptr(grad))
     if rc != 0:
-        raise ValueError("the oracle adjoint covers the incompressible D3Q19 form with the "
-                         "second-order equilibria only")
+        raise ValueError("the oracle adjoint covers the incompressible form only")
     return lam_prev, grad
 
 
 def objective(cfg: Config, f, kind: int):
     """(J, lam_seed, dJ/da explicit) for kind 0 (kinetic energy) or 1 (outlet flux)."""
     lib = _load()
-    f = _f64(f, (NQ,) + cfg.shape)
+    f = _f64(f, (cfg.q,) + cfg.shape)
     lam = np.empty_like(f)
     da = np.zeros(3)
     ref, _keep = cfg._c()
@@ -255,12 +254,12 @@ def objective(cfg: Config, f, kind: int):
 def init_vjp(cfg: Config, u_init, lam0):
     lib = _load()
     u = _f64(u_init, (3,) + cfg.shape)
-    lam0 = _f64(lam0, (NQ,) + cfg.shape)
+    lam0 = _f64(lam0, (cfg.q,) + cfg.shape)
     g = np.empty((3,) + cfg.shape)
     ref, _keep = cfg._c()
     rc = lib.oracle_init_vjp(ref, _ptr(cfg._solid()), _ptr(u), _ptr(lam0), _ptr(g))
     if rc != 0:
-        raise ValueError("the oracle adjoint covers D3Q19 with the second-order equilibria only")
+        raise ValueError("oracle_init_vjp failed")
     return g
 
 

@@ -242,14 +242,21 @@ static double ipow(double x, int n)
 /* Maxwellian moment of exponent e (variance c_s^2 = 1/3), truncated at
  * O(u^3): product of the one-dimensional moments 1, u, u^2 + 1/3, the
  * velocity-free part times rho, every other term times rho0. */
-static double maxwellian_moment3(const int e[3], double rho, double rho0, const double u[3])
+static void moment_coefs(const int e[3], double coef[3][3])
 {
-    double coef[3][3];   /* coef[axis][power] */
+    /* coef[axis][power]: the one-dimensional moment of exponent e[axis] is
+     * sum_power coef * u^power. */
     for (int i = 0; i < 3; ++i) {
         coef[i][0] = e[i] == 0 ? 1.0 : (e[i] == 2 ? 1.0 / 3.0 : 0.0);
         coef[i][1] = e[i] == 1 ? 1.0 : 0.0;
         coef[i][2] = e[i] == 2 ? 1.0 : 0.0;
     }
+}
+
+static double maxwellian_moment3(const int e[3], double rho, double rho0, const double u[3])
+{
+    double coef[3][3];
+    moment_coefs(e, coef);
     double free = coef[0][0] * coef[1][0] * coef[2][0];
     double rest = 0.0;
     for (int a = 0; a < 3; ++a)
@@ -260,6 +267,26 @@ static double maxwellian_moment3(const int e[3], double rho, double rho0, const 
                         ipow(u[2], c);
             }
     return free * rho + rest * rho0;
+}
+
+/* d/du_d of the moment above at fixed rho, rho0: the derivative of each
+ * retained monomial u0^a u1^b u2^c. */
+static double dmaxwellian_moment3_du(const int e[3], double rho0, const double u[3], int d)
+{
+    double coef[3][3];
+    moment_coefs(e, coef);
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) {
+                int pw[3] = {a, b, c};
+                if (a + b + c == 0 || a + b + c > 3 || pw[d] == 0) continue;
+                double t = coef[0][a] * coef[1][b] * coef[2][c];
+                for (int i = 0; i < 3; ++i)
+                    t *= i == d ? pw[i] * ipow(u[i], pw[i] - 1) : ipow(u[i], pw[i]);
+                s += t;
+            }
+    return s * rho0;
 }
 
 /* All 19 values f^eq = M^-1 m(rho, u). */
@@ -310,6 +337,26 @@ static double dfeq_du(const oracle_cfg *cfg, int q, int b, double rho0, const do
     return weight(q) * rho0 * (3.0 * cb - 3.0 * u[b] * cb * cb + 9.0 * cu * cb);
 }
 
+/* d f^eq_q / d u_b for all q: the hand-differentiated forms above, or for the
+ * third-order D3Q19-I, M^-1 times the derivatives of its moments. */
+static void dfeq_du_all(const oracle_cfg *cfg, double rho0, const double u[3], double D[NQ][3])
+{
+    if (cfg->stencil != 27 && cfg->improved == 2) {
+        double dm[19][3];
+        for (int k = 0; k < 19; ++k)
+            for (int b = 0; b < 3; ++b) dm[k][b] = dmaxwellian_moment3_du(Mexp[k], rho0, u, b);
+        for (int q = 0; q < 19; ++q)
+            for (int b = 0; b < 3; ++b) {
+                double v = 0.0;
+                for (int k = 0; k < 19; ++k) v += Minv[q][k] * dm[k][b];
+                D[q][b] = v;
+            }
+        return;
+    }
+    for (int q = 0; q < QN(cfg); ++q)
+        for (int b = 0; b < 3; ++b) D[q][b] = dfeq_du(cfg, q, b, rho0, u);
+}
+
 /* Serial set-up before any parallel region (the third-order construction's
  * moment-matrix inverse). */
 static void oracle_prepare(void) { moment_matrix_inverse(); }
@@ -320,10 +367,13 @@ void oracle_feq(const oracle_cfg *cfg, double rho, double rho0, const double *u,
     feq_all(cfg, rho, rho0, u, out);
 }
 
-void oracle_dfeq_du(const oracle_cfg *cfg, double rho0, const double *u, double *out /*[19][3]*/)
+void oracle_dfeq_du(const oracle_cfg *cfg, double rho0, const double *u, double *out /*[Q][3]*/)
 {
+    oracle_prepare();
+    double D[NQ][3];
+    dfeq_du_all(cfg, rho0, u, D);
     for (int q = 0; q < QN(cfg); ++q)
-        for (int b = 0; b < 3; ++b) out[3 * q + b] = dfeq_du(cfg, q, b, rho0, u);
+        for (int b = 0; b < 3; ++b) out[3 * q + b] = D[q][b];
 }
 
 /* Forcing term F_q = w_q / c_s^2 (c_q . a), c_s^2 = 1/3. */
@@ -332,6 +382,15 @@ static double force_term(const oracle_cfg *cfg, int q)
     double ca = 0.0;
     for (int d = 0; d < 3; ++d) ca += C[q][d] * cfg->accel[d];
     return weight(q) / (1.0 / 3.0) * ca;
+}
+
+/* MRT rate of kept moment k (Sec. 3.2): the conserved moments (order 0, 1)
+ * relax at 1, which leaves them unchanged; order 2 at omega (the viscosity),
+ * order 3 at omega3, order 4 at omega4. */
+static double mrt_rate(const oracle_cfg *cfg, int k)
+{
+    int order = Mexp[k][0] + Mexp[k][1] + Mexp[k][2];
+    return order <= 1 ? 1.0 : (order == 2 ? cfg->omega : (order == 3 ? cfg->omega3 : cfg->omega4));
 }
 
 /* TRT odd rate from Lambda = (1/w+ - 1/2)(1/w- - 1/2). */
@@ -420,8 +479,7 @@ static void collide(const oracle_cfg *cfg, const double g[NQ], double out[NQ])
                 meq[k] += mk * fe[q];
                 mF[k] += mk * force_term(cfg, q);
             }
-            int order = Mexp[k][0] + Mexp[k][1] + Mexp[k][2];
-            double s = order <= 1 ? 1.0 : (order == 2 ? w : (order == 3 ? cfg->omega3 : cfg->omega4));
+            double s = mrt_rate(cfg, k);
             mnew[k] = m[k] - s * (m[k] - meq[k]) + (1.0 - s / 2.0) * mF[k];
         }
         for (int q = 0; q < 19; ++q) {
@@ -553,15 +611,40 @@ void oracle_moments(const oracle_cfg *cfg, const uint8_t *solid, const double *f
 
 /* Full 19x19 Jacobian J[q][r] = d f*_q / d g_r of the collision of one cell,
  * and the derivatives of f* with respect to omega and a. */
+/* Moment k of direction q: c_q^e_k (the MRT moment matrix M[k][q]). */
+static double monomial(int k, int q)
+{
+    double v = 1.0;
+    for (int i = 0; i < 3; ++i)
+        for (int t = 0; t < Mexp[k][i]; ++t) v *= C[q][i];
+    return v;
+}
+
+/* MRT (Sec. 3.2) written on the populations: R = M^-1 S M, and its
+ * derivative with respect to omega, P2 = M^-1 diag(order == 2) M. */
+static void mrt_relaxation(const oracle_cfg *cfg, double R[NQ][NQ], double P2[NQ][NQ])
+{
+    for (int q = 0; q < 19; ++q)
+        for (int r = 0; r < 19; ++r) {
+            double v = 0.0, p2 = 0.0;
+            for (int k = 0; k < 19; ++k) {
+                int order = Mexp[k][0] + Mexp[k][1] + Mexp[k][2];
+                double mk = Minv[q][k] * monomial(k, r);
+                v += mk * mrt_rate(cfg, k);
+                p2 += order == 2 ? mk : 0.0;
+            }
+            R[q][r] = v;
+            P2[q][r] = p2;
+        }
+}
+
 static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double J[NQ][NQ],
                                double dw[NQ], double da[NQ][3])
 {
     double rho, rho0, u[3], fe[NQ], D[NQ][3], dfe_dg[NQ][NQ];
     macroscopic(cfg, g, &rho, &rho0, u);
-    for (int q = 0; q < QN(cfg); ++q) {
-        fe[q] = feq(cfg, q, rho, rho0, u);
-        for (int b = 0; b < 3; ++b) D[q][b] = dfeq_du(cfg, q, b, rho0, u);
-    }
+    feq_all(cfg, rho, rho0, u, fe);
+    dfeq_du_all(cfg, rho0, u, D);
     /* With rho0 = 1: d rho / d g_r = 1, d u_b / d g_r = c_rb, d u_b / d a_b = 1/2. */
     for (int q = 0; q < QN(cfg); ++q)
         for (int r = 0; r < QN(cfg); ++r) {
@@ -570,14 +653,19 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
             dfe_dg[q][r] = v;
         }
     double wp = cfg->omega, wm = omega_minus(cfg);
-    /* Relaxation matrix R = wp P+ + wm P-, P+- = (I +- reversal) / 2. */
-    double R[NQ][NQ];
-    for (int q = 0; q < QN(cfg); ++q)
-        for (int s = 0; s < QN(cfg); ++s) {
-            double pp = 0.5 * ((q == s) + (opposite(q) == s));
-            double pm = 0.5 * ((q == s) - (opposite(q) == s));
-            R[q][s] = cfg->trt ? wp * pp + wm * pm : wp * (q == s);
-        }
+    /* Relaxation matrix R = wp P+ + wm P-, P+- = (I +- reversal) / 2, or the
+     * MRT one. */
+    double R[NQ][NQ], P2[NQ][NQ];
+    if (cfg->mrt) {
+        mrt_relaxation(cfg, R, P2);
+    } else {
+        for (int q = 0; q < QN(cfg); ++q)
+            for (int s = 0; s < QN(cfg); ++s) {
+                double pp = 0.5 * ((q == s) + (opposite(q) == s));
+                double pm = 0.5 * ((q == s) - (opposite(q) == s));
+                R[q][s] = cfg->trt ? wp * pp + wm * pm : wp * (q == s);
+            }
+    }
     for (int q = 0; q < QN(cfg); ++q)
         for (int r = 0; r < QN(cfg); ++r) {
             double v = (q == r) - R[q][r];
@@ -589,13 +677,26 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
         for (int b = 0; b < 3; ++b) {
             double v = 0.0;
             for (int s = 0; s < QN(cfg); ++s) v += R[q][s] * 0.5 * D[s][b];
-            da[q][b] = v + (1.0 - fm / 2.0) * 3.0 * weight(q) * C[q][b];
+            if (cfg->mrt) {
+                /* force term M^-1 (I - S/2) M F = (I - R/2) F, F_s = 3 w_s c_s.a */
+                v += 3.0 * weight(q) * C[q][b];
+                for (int s = 0; s < 19; ++s) v -= 0.5 * R[q][s] * 3.0 * weight(s) * C[s][b];
+                da[q][b] = v;
+            } else {
+                da[q][b] = v + (1.0 - fm / 2.0) * 3.0 * weight(q) * C[q][b];
+            }
         }
     }
-    /* d f* / d omega.  For TRT, omega_minus follows omega through fixed Lambda. */
+    /* d f* / d omega.  For TRT, omega_minus follows omega through fixed Lambda;
+     * for MRT only the second-order moments' rate moves: -P2 (g - f^eq + F/2). */
     for (int q = 0; q < QN(cfg); ++q) {
         int qb = opposite(q);
-        if (!cfg->trt) {
+        if (cfg->mrt) {
+            double v = 0.0;
+            for (int s = 0; s < 19; ++s)
+                v -= P2[q][s] * (g[s] - fe[s] + 0.5 * force_term(cfg, s));
+            dw[q] = v;
+        } else if (!cfg->trt) {
             dw[q] = -(g[q] - fe[q]) - 0.5 * force_term(cfg, q);
         } else {
             double gp = 0.5 * (g[q] + g[qb]), gm = 0.5 * (g[q] - g[qb]);
@@ -610,13 +711,14 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
 }
 
 /* lam_prev = (d step / d f_t)^T lam_next.  grad[0] += dJ/domega,
- * grad[1..3] += dJ/da (the contribution of this step).  Returns -1 for the
- * compressible form, D3Q27 and the third-order equilibrium, which have no
- * adjoint here. */
+ * grad[1..3] += dJ/da (the contribution of this step).  Every stencil,
+ * equilibrium and collision of the forward step; returns -1 for the
+ * compressible form, which has no adjoint here. */
 int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const double *f_t,
                         const double *lam_next, double *lam_prev, double *grad)
 {
-    if (cfg->compressible || cfg->stencil == 27 || cfg->improved == 2 || cfg->mrt) return -1;
+    if (cfg->compressible) return -1;
+    oracle_prepare();
     int64_t n = ncells_of(cfg);
     double *plane = (double *)calloc((size_t)cfg->nz * 4, sizeof(double));
 #pragma omp parallel for schedule(static)
@@ -703,7 +805,7 @@ double oracle_objective(const oracle_cfg *cfg, const uint8_t *solid, int kind, c
 int oracle_init_vjp(const oracle_cfg *cfg, const uint8_t *solid, const double *u_init,
                     const double *lam0, double *grad_u)
 {
-    if (cfg->stencil == 27 || cfg->improved == 2) return -1;
+    oracle_prepare();
     int64_t n = ncells_of(cfg);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
@@ -712,9 +814,11 @@ int oracle_init_vjp(const oracle_cfg *cfg, const uint8_t *solid, const double *u
             continue;
         }
         double u[3] = {u_init[c], u_init[n + c], u_init[2 * n + c]};
+        double D[NQ][3];
+        dfeq_du_all(cfg, 1.0, u, D);
         for (int b = 0; b < 3; ++b) {
             double v = 0.0;
-            for (int q = 0; q < QN(cfg); ++q) v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);
+            for (int q = 0; q < QN(cfg); ++q) v += lam0[q * n + c] * D[q][b];
             grad_u[b * n + c] = v;
         }
     }

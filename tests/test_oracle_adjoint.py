@@ -164,3 +164,121 @@ def test_compressible_adjoint_is_refused():
     f = _state(oracle.Config(2, 2, 2, omega=1.0), 1)
     with pytest.raises(ValueError):
         oracle.adjoint_step(cfg, f, f)
+
+
+# --------------------------------------------------------------------------
+# The adjoint of the widened forward path: D3Q27 (Sec. 2.3, 3.1), the
+# third-order D3Q19-I (Sec. 3.2 carried to O(u^3)) and MRT with Maxwellian
+# moments (Sec. 3.2).  The third-order step is not quadratic in f and a, so
+# these pins use fourth-order central differences throughout.
+# --------------------------------------------------------------------------
+
+def _wide_cfgs():
+    solid = np.zeros((4, 5, 6), np.uint8)
+    solid[1:3, 2, 2:4] = 1
+    base = dict(nx=6, ny=5, nz=4, periodic=(1, 0, 1), omega=1.45, magic=3 / 16,
+                accel=(2e-4, -1e-4, 5e-5), solid=solid)
+    return [
+        ("Q27-SRT", oracle.Config(stencil=27, improved=0, **base)),
+        ("Q27-TRT", oracle.Config(stencil=27, improved=0, trt=True, **base)),
+        ("I3-SRT", oracle.Config(improved=2, **base)),
+        ("I3-TRT", oracle.Config(improved=2, trt=True, **base)),
+        ("MRT-S", oracle.Config(improved=0, mrt=True, omega3=1.7, omega4=0.9, **base)),
+        ("MRT-I", oracle.Config(improved=1, mrt=True, omega3=1.7, omega4=0.9, **base)),
+        ("MRT-I3", oracle.Config(improved=2, mrt=True, omega3=0.8, omega4=1.6, **base)),
+    ]
+
+
+def _wstate(cfg, seed, amp=0.02):
+    w = oracle.velocity_set(cfg.stencil)[1]
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-0.05, 0.05, size=(3,) + cfg.shape)
+    f = oracle.init(cfg, u, rho=1.0 + 0.01 * rng.standard_normal(cfg.shape))
+    f = f + amp * w[:, None, None, None] * rng.standard_normal(f.shape)
+    if cfg.solid is not None:
+        f[:, cfg.solid.astype(bool)] = w[:, None]
+    return f, w
+
+
+def _wreplace(cfg, **kw):
+    d = dict(nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, periodic=cfg.periodic, improved=cfg.improved,
+             trt=cfg.trt, compressible=cfg.compressible, omega=cfg.omega, magic=cfg.magic,
+             accel=cfg.accel, solid=cfg.solid, stencil=cfg.stencil, mrt=cfg.mrt,
+             omega3=cfg.omega3, omega4=cfg.omega4)
+    d.update(kw)
+    return oracle.Config(**d)
+
+
+WIDE = _wide_cfgs()
+
+
+@pytest.mark.parametrize("name,cfg", WIDE, ids=[n for n, _ in WIDE])
+def test_wide_adjoint_step_dot_product(name, cfg):
+    rng = np.random.default_rng(31)
+    f, w = _wstate(cfg, 32)
+    v = w[:, None, None, None] * rng.standard_normal(f.shape)
+    lam = rng.standard_normal(f.shape)
+    jvp = _fd4(lambda s: (oracle.step(cfg, f + s * v) * lam).sum(), 1e-3)
+    lam_prev, _ = oracle.adjoint_step(cfg, f, lam)
+    rhs = (v * lam_prev).sum()
+    assert abs(jvp - rhs) <= 1e-10 * (abs(jvp) + np.abs(v).sum()), (jvp, rhs)
+
+
+@pytest.mark.parametrize("name,cfg", WIDE, ids=[n for n, _ in WIDE])
+def test_wide_adjoint_step_parameter_gradients(name, cfg):
+    rng = np.random.default_rng(33)
+    f, _ = _wstate(cfg, 34)
+    lam = rng.standard_normal(f.shape)
+    _, grad = oracle.adjoint_step(cfg, f, lam)
+
+    def J(c):
+        return (oracle.step(c, f) * lam).sum()
+
+    for b in range(3):
+        def shifted(s, b=b):
+            a = list(cfg.accel)
+            a[b] += s
+            return J(_wreplace(cfg, accel=tuple(a)))
+        fd = _fd4(shifted, 1e-4)
+        assert abs(fd - grad[1 + b]) <= 1e-9 * max(1.0, abs(fd)), (b, fd, grad[1 + b])
+    fd = _fd4(lambda s: J(_wreplace(cfg, omega=cfg.omega + s)), 1e-4)
+    assert abs(fd - grad[0]) <= 1e-9 * max(1.0, abs(fd)), (fd, grad[0])
+
+
+@pytest.mark.parametrize("name,cfg", WIDE, ids=[n for n, _ in WIDE])
+def test_wide_rollout_gradient_against_finite_differences(name, cfg):
+    """Gradient of the kinetic energy after T = 5 steps from f^eq(1, u_init)
+    with respect to u_init (random direction), a and omega: the init VJP,
+    the adjoint steps and the objective seed of the widened path together."""
+    T, kind = 5, 0
+    rng = np.random.default_rng(35)
+    u0 = rng.uniform(-0.04, 0.04, size=(3,) + cfg.shape)
+    J, gu, gw, ga = oracle.gradient(cfg, u0, T, kind)
+    v = rng.standard_normal(u0.shape)
+    fd = _fd4(lambda s: oracle.run_objective(cfg, u0 + s * v, T, kind), 1e-5)
+    assert abs(fd - (gu * v).sum()) <= 1e-8 * max(1e-3, abs(fd)), (fd, (gu * v).sum())
+    for b in range(3):
+        def shifted(s, b=b):
+            a = list(cfg.accel)
+            a[b] += s
+            return oracle.run_objective(_wreplace(cfg, accel=tuple(a)), u0, T, kind)
+        fd = _fd4(shifted, 1e-5)
+        assert abs(fd - ga[b]) <= 1e-8 * max(1e-3, abs(fd)), (b, fd, ga[b])
+    fd = _fd4(lambda s: oracle.run_objective(_wreplace(cfg, omega=cfg.omega + s), u0, T, kind),
+              1e-5)
+    assert abs(fd - gw) <= 1e-8 * max(1e-3, abs(fd)), (fd, gw)
+
+
+def test_third_order_dfeq_du_against_differences():
+    """d f^eq / d u of the third-order D3Q19-I: the oracle differentiates its
+    moments; compare with central differences of the equilibrium itself."""
+    cfg = oracle.Config(1, 1, 1, improved=2)
+    rng = np.random.default_rng(36)
+    for _ in range(5):
+        u = rng.uniform(-0.2, 0.2, 3)
+        D = oracle.dfeq_du(cfg, u)
+        for b in range(3):
+            e = np.zeros(3)
+            e[b] = 1.0
+            fd = _fd4(lambda s: oracle.feq(cfg, 1.0, u + s * e), 1e-4)
+            np.testing.assert_allclose(D[:, b], fd, rtol=0, atol=1e-12)

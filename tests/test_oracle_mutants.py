@@ -65,8 +65,15 @@ MUTANTS = [
      "mnew[k] = m[k] - s * (m[k] - meq[k]) + mF[k];"),
     ("MRT third-order moments take the fourth-order rate",
      "(order == 3 ? cfg->omega3 : cfg->omega4)", "(order == 3 ? cfg->omega4 : cfg->omega4)"),
-    ("init VJP reads the rest population only", "v += lam0[q * n + c] * dfeq_du(cfg, q, b, 1.0, u);",
-     "v += lam0[c] * dfeq_du(cfg, q, b, 1.0, u);"),
+    ("init VJP reads the rest population only", "v += lam0[q * n + c] * D[q][b];",
+     "v += lam0[c] * D[q][b];"),
+    ("MRT adjoint force term without (I - R/2)",
+     "v -= 0.5 * R[q][s] * 3.0 * weight(s) * C[s][b];", "v -= 0.0 * R[q][s] * 3.0 * weight(s) * C[s][b];"),
+    ("MRT d/domega moves the third-order rate", "p2 += order == 2 ? mk : 0.0;",
+     "p2 += order == 3 ? mk : 0.0;"),
+    ("third-order moment derivative drops the power factor",
+     "t *= i == d ? pw[i] * ipow(u[i], pw[i] - 1) : ipow(u[i], pw[i]);",
+     "t *= i == d ? ipow(u[i], pw[i] - 1) : ipow(u[i], pw[i]);"),
 ]
 
 

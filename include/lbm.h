@@ -73,7 +73,7 @@ typedef enum {
 enum { LBM_EQ_STANDARD = 0, LBM_EQ_IMPROVED = 1,
        /* IMPROVED3: the same construction carried to third order in u, i.e.
         * the equilibrium whose moments are the D3Q19-I column of Table 1
-        * (Sec. 3.1) including its O(u^3) terms.  Forward path only. */
+        * (Sec. 3.1) including its O(u^3) terms. */
        LBM_EQ_IMPROVED3 = 2 };
 
 /* Collision.  SRT: eq. lb_srt_with_forces (Sec. 2.3).  TRT: two relaxation
@@ -86,8 +86,7 @@ enum { LBM_EQ_STANDARD = 0, LBM_EQ_IMPROVED = 1,
  * e_i in {0,1,2} except the 8 that Sec. 3.2 drops), with m_eq the moments of
  * the chosen equilibrium (for IMPROVED: the Maxwellian ones).  Rates:
  * second-order moments omega, third-order mrt_omega3, fourth-order
- * mrt_omega4 (conserved moments are unaffected by their rate).  Forward path
- * only. */
+ * mrt_omega4 (conserved moments are unaffected by their rate). */
 enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2 };
 
 /* Storage types of the PDF state. */
@@ -127,7 +126,7 @@ typedef struct {
     int32_t adjoint_dtype;    /* LBM_F64 (only with dtype LBM_F64) or LBM_F32      */
     int32_t stencil;          /* 19 (D3Q19) or 27 (D3Q27; its single equilibrium
                                  is the moment-matched = standard one, Sec. 3.1,
-                                 whatever `equilibrium` says; forward only)      */
+                                 whatever `equilibrium` says)                    */
     double omega;             /* SRT rate or TRT even rate, 0 < omega < 2         */
     double trt_magic;         /* TRT Lambda > 0; ignored for SRT                  */
     double accel[3];          /* body acceleration a; F_q = 3 w_q c_q.a (Sec. 2.3) */
@@ -236,9 +235,10 @@ int lbm_watchdog(lbm_ctx *c, double rel_tol);
 int lbm_set_rates(lbm_ctx *c, double omega, const double *accel);
 
 /* ------------------------------------------------------------------------ */
-/* Adjoint (not in the paper): exact transpose of one two-grid step.         */
-/* D3Q19, incompressible form (compressible == 0) only; otherwise            */
-/* LBM_ESTATE.                                                               */
+/* Adjoint (not in the paper): exact transpose of one two-grid step, for    */
+/* every stencil, equilibrium and collision of the forward step.  Adjoint   */
+/* fields hold Q arrays like a state.  Incompressible form                  */
+/* (compressible == 0) only; otherwise LBM_ESTATE.                           */
 /* ------------------------------------------------------------------------ */
 
 /* lam_prev = (d step / d f_t)^T lam_next for the step f_t -> f_{t+1}.
@@ -248,7 +248,8 @@ int lbm_set_rates(lbm_ctx *c, double omega, const double *accel);
  *   lam_prev  device adjoint field at t (written; distinct from lam_next)
  *   grad      device double[4] or NULL: += dJ/domega, dJ/da_x, dJ/da_y,
  *             dJ/da_z of this step (FP64, deterministic order).  For TRT,
- *             omega_minus follows omega at fixed Lambda.
+ *             omega_minus follows omega at fixed Lambda; for MRT omega is
+ *             the rate of the second-order moments (mrt_omega3/4 fixed).
  * Per cell: gather as the forward step, mu = J_C^T lam_next, then write mu_r
  * to lam_prev[r] at x - c_r, or to lam_prev[opposite(r)] at x when x - c_r
  * is a wall or solid (every slot is written exactly once; no atomics).

@@ -42,6 +42,9 @@ class RolloutConfig:
     scale: float = 0.0
     rounding: str = "nearest"
     seed: int = 0
+    stencil: int = 19
+    mrt_omega3: float = 1.0
+    mrt_omega4: float = 1.0
 
     @property
     def segment(self) -> int:
@@ -58,7 +61,9 @@ class _Rollout(torch.autograd.Function):
                       equilibrium=cfg.equilibrium, collision=cfg.collision, dtype=cfg.dtype,
                       omega=float(omega), trt_magic=cfg.trt_magic,
                       accel=tuple(float(v) for v in accel.detach().cpu()), scale=cfg.scale,
-                      rounding=cfg.rounding, seed=cfg.seed, device=u_init.device)
+                      rounding=cfg.rounding, seed=cfg.seed, stencil=cfg.stencil,
+                      mrt_omega3=cfg.mrt_omega3, mrt_omega4=cfg.mrt_omega4,
+                      device=u_init.device)
         C = cfg.segment
         ckpts = {}
         for t in range(cfg.steps):

@@ -198,7 +198,7 @@ extern "C" int lbm_state_bytes(const lbm_params *p, size_t *bytes) {
 extern "C" int lbm_adjoint_bytes(const lbm_params *p, size_t *bytes) {
     std::string why;
     if (validate(p, why) != LBM_OK || !bytes) return LBM_EINVAL;
-    *bytes = (size_t)Q * qstride_of(p) * dtype_size(p->adjoint_dtype);
+    *bytes = (size_t)p->stencil * qstride_of(p) * dtype_size(p->adjoint_dtype);
     return LBM_OK;
 }
 
@@ -235,7 +235,7 @@ static void invert(double *a, int n) {
 // ones sum_p 2 c_q^e (n_q - n_qbar)/2 (q = 2p+1, qbar = q+1), so
 // M_e = [c_0^e | 2 c_q^e] (10 x 10) and M_o = [2 c_q^e] (9 x 9); the
 // relaxation in pair coordinates is K = M^-1 S M.
-static void mrt_matrices(const lbm_params &p, double ke[100], double ko[81]) {
+static void mrt_matrices(const lbm_params &p, double ke[100], double ko[81], double pe2[100]) {
     static const int even[10][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0},
                                     {1, 0, 1}, {0, 1, 1}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}};
     static const int odd[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 1, 0}, {2, 0, 1},
@@ -274,6 +274,10 @@ static void mrt_matrices(const lbm_params &p, double ke[100], double ko[81]) {
     }
     relax(me, se, 10, ke);
     relax(mo, so, 9, ko);
+    // d K_e / d omega = M_e^-1 diag(order == 2) M_e (the adjoint's dJ/domega)
+    double s2[10];
+    for (int k = 0; k < 10; ++k) s2[k] = even[k][0] + even[k][1] + even[k][2] == 2 ? 1.0 : 0.0;
+    relax(me, s2, 10, pe2);
 }
 
 // Relaxation and force constants of the update in both precisions.
@@ -300,7 +304,7 @@ static void set_coll(lbm_ctx *c) {
     d.s = c->scale;
     d.inv_s = 1.0 / c->scale;
     d.compressible = p.compressible;
-    if (p.collision == LBM_MRT) mrt_matrices(p, d.ke, d.ko);
+    if (p.collision == LBM_MRT) mrt_matrices(p, d.ke, d.ko, d.pe2);
     Coll<float> f = {};
     f.wp = (float)d.wp;
     f.wm = (float)d.wm;
@@ -314,6 +318,7 @@ static void set_coll(lbm_ctx *c) {
     f.inv_s = (float)d.inv_s;
     f.compressible = d.compressible;
     for (int i = 0; i < 100; ++i) f.ke[i] = (float)d.ke[i];
+    for (int i = 0; i < 100; ++i) f.pe2[i] = (float)d.pe2[i];
     for (int i = 0; i < 81; ++i) f.ko[i] = (float)d.ko[i];
     c->coll.d = d;
     c->coll.f = f;
@@ -564,45 +569,38 @@ extern "C" int lbm_set_rates(lbm_ctx *c, double omega, const double *accel) {
 extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next,
                                 void *lam_prev, double *grad) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3 || c->p.collision == LBM_MRT)
-        return fail(c, LBM_ESTATE,
-                    "the adjoint is written for D3Q19 SRT/TRT with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
     if (!state_t || !lam_next || !lam_prev || lam_next == lam_prev)
         return fail(c, LBM_EINVAL, "state_t, lam_next, lam_prev must be set, lam_next != lam_prev");
-    hipError_t e = launch_adjoint(c->g, c->p.dtype, c->p.adjoint_dtype, c->p.equilibrium, c->gen,
-                                  c->coll, state_t, lam_next, lam_prev, grad, c->sc, c->stream);
+    hipError_t e = launch_adjoint(c->g, c->p.stencil, c->p.dtype, c->p.adjoint_dtype,
+                                  c->p.equilibrium, c->p.collision == LBM_MRT, c->gen, c->coll,
+                                  state_t, lam_next, lam_prev, grad, c->sc, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return LBM_OK;
 }
 
 extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *out, void *lam) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3 || c->p.collision == LBM_MRT)
-        return fail(c, LBM_ESTATE,
-                    "the adjoint is written for D3Q19 SRT/TRT with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "objectives are defined for the incompressible form only");
     if (kind != LBM_OBJ_KINETIC_ENERGY && kind != LBM_OBJ_OUTLET_FLUX)
         return fail(c, LBM_EINVAL, "unknown objective kind %d", kind);
     if (!state || !out || !lam) return fail(c, LBM_EINVAL, "state, out and lam must be set");
-    hipError_t e = launch_objective(c->g, c->p.dtype, c->p.adjoint_dtype, kind, 1.0 / c->scale,
-                                    c->coll.d.ah, state, out, lam, c->sc, c->stream);
+    hipError_t e = launch_objective(c->g, c->p.stencil, c->p.dtype, c->p.adjoint_dtype, kind,
+                                    1.0 / c->scale, c->coll.d.ah, state, out, lam, c->sc,
+                                    c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "objective");
     return LBM_OK;
 }
 
 extern "C" int lbm_init_vjp(lbm_ctx *c, const double *u_init, const void *lam0, double *grad_u) {
     if (!c) return LBM_EINVAL;
-    if (c->p.stencil != 19 || c->p.equilibrium == LBM_EQ_IMPROVED3 || c->p.collision == LBM_MRT)
-        return fail(c, LBM_ESTATE,
-                    "the adjoint is written for D3Q19 SRT/TRT with the second-order equilibria");
     if (c->p.compressible)
         return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
     if (!u_init || !lam0 || !grad_u) return fail(c, LBM_EINVAL, "u_init, lam0, grad_u must be set");
-    hipError_t e = launch_init_vjp(c->g, c->p.adjoint_dtype, c->p.equilibrium, u_init, lam0,
-                                   grad_u, c->stream);
+    hipError_t e = launch_init_vjp(c->g, c->p.stencil, c->p.adjoint_dtype, c->p.equilibrium,
+                                   u_init, lam0, grad_u, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init_vjp");
     return LBM_OK;
 }

@@ -5,6 +5,7 @@
 // F_q = 3 w_q c_q.a, the force-shifted velocity of eq. macroscopic_vel_shift,
 // the standard (Sec. 2.2) or improved (Sec. 3.2, eq. new_d3q19_equilibrium)
 // equilibrium, half-way bounce-back and periodic wrap (Sec. 5.1).
+#include "dispatch.h"
 #include "launch.h"
 #include "reduce.h"
 
@@ -406,35 +407,6 @@ __global__ __launch_bounds__(kBlock) void k_copy(const u32x4 *__restrict__ src,
 // Launchers
 // ---------------------------------------------------------------------------
 
-template <int DT>
-static const Coll<typename Store<DT>::R> &pick(const CollBoth &P);
-template <>
-const Coll<double> &pick<LBM_F64>(const CollBoth &P) { return P.d; }
-template <>
-const Coll<float> &pick<LBM_F32>(const CollBoth &P) { return P.f; }
-template <>
-const Coll<float> &pick<LBM_F32_SHIFTED>(const CollBoth &P) { return P.f; }
-template <>
-const Coll<float> &pick<LBM_F16_SHIFTED>(const CollBoth &P) { return P.f; }
-template <>
-const Coll<float> &pick<LBM_BF16_SHIFTED>(const CollBoth &P) { return P.f; }
-
-#define LBM_DISPATCH_DT(dtype, BODY)                                  \
-    switch (dtype) {                                                  \
-    case LBM_F64: { constexpr int DT = LBM_F64; BODY; } break;                 \
-    case LBM_F32: { constexpr int DT = LBM_F32; BODY; } break;                 \
-    case LBM_F32_SHIFTED: { constexpr int DT = LBM_F32_SHIFTED; BODY; } break; \
-    case LBM_F16_SHIFTED: { constexpr int DT = LBM_F16_SHIFTED; BODY; } break; \
-    case LBM_BF16_SHIFTED: { constexpr int DT = LBM_BF16_SHIFTED; BODY; } break; \
-    default: return hipErrorInvalidValue;                             \
-    }
-
-// D3Q27 has one equilibrium (the standard form, Sec. 3.1).
-#define LBM_DISPATCH_EQ(eq, BODY)                                                              \
-    if (qn == 27) { constexpr int QN = 27; constexpr int EQ = LBM_EQ_STANDARD; BODY; }         \
-    else if (eq == LBM_EQ_IMPROVED) { constexpr int QN = 19; constexpr int EQ = LBM_EQ_IMPROVED; BODY; } \
-    else if (eq == LBM_EQ_IMPROVED3) { constexpr int QN = 19; constexpr int EQ = LBM_EQ_IMPROVED3; BODY; } \
-    else { constexpr int QN = 19; constexpr int EQ = LBM_EQ_STANDARD; BODY; }
 
 // Stochastic rounding exists for the 16-bit formats only.
 #define LBM_DISPATCH_SR(BODY)                                                       \
@@ -442,19 +414,6 @@ const Coll<float> &pick<LBM_BF16_SHIFTED>(const CollBoth &P) { return P.f; }
         if (sr) { constexpr bool SR = true; BODY; }                                 \
         else { constexpr bool SR = false; BODY; }                                   \
     } else { constexpr bool SR = false; BODY; }
-
-// MRT exists for D3Q19 only.
-#define LBM_DISPATCH_MRT(BODY)                                          \
-    if (QN == 19 && mrt) { constexpr bool MRT = true; BODY; }           \
-    else { constexpr bool MRT = false; BODY; }
-
-#define LBM_DISPATCH_Q(BODY)                              \
-    if (qn == 27) { constexpr int QN = 27; BODY; }        \
-    else { constexpr int QN = 19; BODY; }
-
-#define LBM_DISPATCH_GEN(gen, BODY)                      \
-    if (gen) { constexpr bool GEN = true; BODY; }        \
-    else { constexpr bool GEN = false; BODY; }
 
 hipError_t launch_init(const Geom &g, int qn, int dtype, int eq, int compressible, Layout layout,
                        const double *rho, const double *u, void *A, void *B, double s,

@@ -1,6 +1,6 @@
 // Host-side launch interface between the C ABI (api.hip) and the kernel
 // translation units (forward.hip, adjoint.hip).  qn is the stencil size (19
-// or 27); the adjoint launchers are D3Q19 only.
+// or 27).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,6 +23,15 @@ struct CollBoth {
     Coll<double> d;
     Coll<float> f;
 };
+
+// The parameters in the compute precision of storage type DT.
+template <int DT>
+inline const Coll<typename Store<DT>::R> &pick(const CollBoth &P) {
+    if constexpr (DT == LBM_F64)
+        return P.d;
+    else
+        return P.f;
+}
 
 // Reduction scratch: nblocks x 4 doubles of block partials, a two-half
 // staging area for the multi-pass final reduction, and a small result slot.
@@ -57,14 +66,14 @@ hipError_t launch_set(const Geom &g, int qn, int dtype, Layout layout, double s,
 hipError_t launch_moments(const Geom &g, int qn, int dtype, Layout layout, double inv_s,
                           int compressible, const double ah[3], const void *A, double *rho,
                           double *u, const Scratch &sc, hipStream_t st);
-hipError_t launch_adjoint(const Geom &g, int dtype, int ltype, int eq, bool gen,
+hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, bool mrt, bool gen,
                           const CollBoth &P, const void *state, const void *lam_next,
                           void *lam_prev, double *grad, const Scratch &sc, hipStream_t st);
-hipError_t launch_objective(const Geom &g, int dtype, int ltype, int kind, double inv_s,
+hipError_t launch_objective(const Geom &g, int qn, int dtype, int ltype, int kind, double inv_s,
                             const double ah[3], const void *state, double *out, void *lam,
                             const Scratch &sc, hipStream_t st);
-hipError_t launch_init_vjp(const Geom &g, int ltype, int eq, const double *u, const void *lam0,
-                           double *grad_u, hipStream_t st);
+hipError_t launch_init_vjp(const Geom &g, int qn, int ltype, int eq, const double *u,
+                           const void *lam0, double *grad_u, hipStream_t st);
 
 // Sum (op 0) or max (op 1) of nvals columns of nblocks partials into out
 // (accumulate: out += result; else out = result).  Passes of 1024-way folds,

@@ -389,6 +389,7 @@ struct Coll {
     // [rest, 9 pair sums] and the odd part [9 pair differences], row-major.
     R ke[100];
     R ko[81];
+    R pe2[100];     // d K_e / d omega (MRT adjoint)
 };
 
 // Moments of shifted PDFs: drho = sum d, j = sum c d.
@@ -439,6 +440,62 @@ struct Poly {
         O3[6] = -xz * cu[6];
         O3[7] = yz * cu[7];
         O3[8] = -yz * cu[8];
+    }
+
+    // Gradients with respect to u, for the adjoint.  Even parts:
+    // standard 9 (c.u) c - 3 u; improved axis a: 12 u_a e_a - 6 u; improved
+    // edge (a, b): 9 (c.u) c - 3 (u_a e_a + u_b e_b).  The rest part's
+    // gradient is g0 u with g0 = rest_grad<EQ, NP>().
+    template <int EQ, int NP>
+    static constexpr double rest_grad() {
+        return ((EQ == LBM_EQ_IMPROVED || EQ == LBM_EQ_IMPROVED3) && NP == 9) ? -2.0 : -3.0;
+    }
+    template <typename R, int EQ, int NP>
+    static __device__ __forceinline__ void grad_even(R ux, R uy, R uz, const R (&cu)[NP],
+                                                     R (&gE)[NP][3]) {
+        const R u[3] = {ux, uy, uz};
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int c[3] = {kC[2 * p + 1].x, kC[2 * p + 1].y, kC[2 * p + 1].z};
+            if ((EQ == LBM_EQ_IMPROVED || EQ == LBM_EQ_IMPROVED3) && NP == 9) {
+                if (p < 3) {
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        gE[p][b] = R(-6) * u[b] + (b == p ? R(12) * u[b] : R(0));
+                } else {
+                    const R k = R(9) * cu[p];
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        gE[p][b] = k * R(c[b]) - (c[b] != 0 ? R(3) * u[b] : R(0));
+                }
+            } else {
+                const R k = R(9) * cu[p];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) gE[p][b] = k * R(c[b]) - R(3) * u[b];
+            }
+        }
+    }
+    // Cubic odd terms of the third-order improved equilibrium: axis a,
+    // d/du_a = -9 (u^2 - u_a^2), d/du_b = -18 u_a u_b; edge with components
+    // c_b = +-1: d/du_b = 9 c_b ((c.u)^2 - u_b^2), 0 along its zero component.
+    template <typename R>
+    static __device__ __forceinline__ void grad_odd3(R ux, R uy, R uz, const R (&cu)[9],
+                                                     R (&gO3)[9][3]) {
+        const R u[3] = {ux, uy, uz};
+        const R uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                gO3[p][b] = b == p ? R(-9) * (uu - u[p] * u[p]) : R(-18) * u[p] * u[b];
+#pragma unroll
+        for (int p = 3; p < 9; ++p) {
+            const int c[3] = {kC[2 * p + 1].x, kC[2 * p + 1].y, kC[2 * p + 1].z};
+            const R c2 = cu[p] * cu[p];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                gO3[p][b] = c[b] != 0 ? R(9 * c[b]) * (c2 - u[b] * u[b]) : R(0);
+        }
     }
 
     template <typename R, int EQ, int NP = 9>
@@ -556,85 +613,141 @@ __device__ __forceinline__ void collide(R (&d)[QN], const Coll<R> &P) {
 }
 
 // Adjoint of one cell (incompressible): on entry lam = lam_{t+1}(x), d = the
-// gathered state g - w.  On exit lam = mu = J_C^T lam_{t+1}.  acc gets
-// += dJ/domega and dJ/da of this cell.
-template <typename R, int EQ, typename A>
-__device__ __forceinline__ void adjoint_cell(const R (&d)[Q], R (&lam)[Q], const Coll<R> &P,
+// gathered shifted PDFs g - w; on exit lam = mu = (d f*/d g)^T lam_{t+1};
+// acc += dJ/domega and dJ/da of this cell.
+// With L = sum_q lam_q f*_q written in pair form, the relaxation enters only
+// through the relaxed even and odd parts of lam: nu0 (rest), nu+_p, nu-_p
+// (omega lam+ and omega_minus lam- for SRT/TRT; halves of K_e^T [lam_0,
+// lam_q + lam_qbar] and K_o^T [lam_q - lam_qbar] for MRT), and the
+// equilibrium through its gradient in u:
+//   mu_0 = lam_0 - nu0 + S,  mu_q/qbar = lam_q/qbar - (nu+ +/- nu-) + S +/- c.V
+//   S = w_0 nu0 + sum 2 w nu+,  V = w_0 nu0 dE_0/du + sum 2 w (nu+ dE_p/du + nu- dO_p/du).
+template <typename R, int EQ, int QN, bool MRT, typename A>
+__device__ __forceinline__ void adjoint_cell(const R (&d)[QN], R (&lam)[QN], const Coll<R> &P,
                                              A (&acc)[4]) {
+    constexpr int NP = (QN - 1) / 2;
+    constexpr bool CUBIC = EQ == LBM_EQ_IMPROVED3 && NP == 9;
     R drho, jx, jy, jz;
-    moments(d, drho, jx, jy, jz);
+    moments<R, QN>(d, drho, jx, jy, jz);
     const R ux = jx + P.ah[0], uy = jy + P.ah[1], uz = jz + P.ah[2];
-    R cu[9], E[9], E0;
-    Poly::even<R, EQ>(ux, uy, uz, cu, E, E0);
-    // gradient of the even parts with respect to u
-    // standard: 9 (c.u) c - 3 u; improved axis a: 12 u_a e_a - 6 u;
-    // improved edge (a, b): 9 (c.u) c - 3 (u_a e_a + u_b e_b); rest -3u / -2u.
-    R gE[9][3];
-    const R g0s = (EQ == LBM_EQ_IMPROVED) ? R(-2) : R(-3);
-    const R cxp[9] = {1, 0, 0, 1, 1, 1, 1, 0, 0};
-    const R cyp[9] = {0, 1, 0, 1, -1, 0, 0, 1, 1};
-    const R czp[9] = {0, 0, 1, 0, 0, 1, -1, 1, -1};
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-        if (EQ == LBM_EQ_IMPROVED) {
-            if (p < 3) {
-                gE[p][0] = R(-6) * ux + (p == 0 ? R(12) * ux : R(0));
-                gE[p][1] = R(-6) * uy + (p == 1 ? R(12) * uy : R(0));
-                gE[p][2] = R(-6) * uz + (p == 2 ? R(12) * uz : R(0));
-            } else {
-                const R k = R(9) * cu[p];
-                gE[p][0] = k * cxp[p] - (cxp[p] != R(0) ? R(3) * ux : R(0));
-                gE[p][1] = k * cyp[p] - (cyp[p] != R(0) ? R(3) * uy : R(0));
-                gE[p][2] = k * czp[p] - (czp[p] != R(0) ? R(3) * uz : R(0));
-            }
-        } else {
-            const R k = R(9) * cu[p];
-            gE[p][0] = k * cxp[p] - R(3) * ux;
-            gE[p][1] = k * cyp[p] - R(3) * uy;
-            gE[p][2] = k * czp[p] - R(3) * uz;
-        }
+    R cu[NP], E[NP], E0;
+    Poly::even<R, EQ, NP>(ux, uy, uz, cu, E, E0);
+    R gE[NP][3];
+    Poly::grad_even<R, EQ, NP>(ux, uy, uz, cu, gE);
+    R O3[9], gO3[9][3];
+    if constexpr (CUBIC) {
+        Poly::odd3<R>(ux, uy, uz, cu, O3);
+        Poly::grad_odd3<R>(ux, uy, uz, cu, gO3);
     }
-    const R w0 = R(1.0 / 3.0);
+    const R g0s = R(Poly::rest_grad<EQ, NP>());
+    const R w0 = R(wq(QN, 0));
+    R nu0, nup[NP], num[NP];
+    if constexpr (MRT && QN == 19) {
+        R le[10], lo[9];
+        le[0] = lam[0];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            le[p + 1] = lam[2 * p + 1] + lam[2 * p + 2];
+            lo[p] = lam[2 * p + 1] - lam[2 * p + 2];
+        }
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            R v = R(0);
+#pragma unroll
+            for (int i = 0; i < 10; ++i) v += P.ke[10 * i + j] * le[i];
+            if (j == 0)
+                nu0 = v;
+            else
+                nup[j - 1] = R(0.5) * v;
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            R v = R(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v += P.ko[9 * i + j] * lo[i];
+            num[j] = R(0.5) * v;
+        }
+    } else {
+        nu0 = P.wp * lam[0];   // nu+_p, nu-_p follow in the pair loop
+    }
     // rest
-    const R nu0 = P.wp * lam[0];
     const R n0 = d[0] - w0 * (drho + E0);
     R S0 = w0 * nu0;
     R Vx = w0 * nu0 * g0s * ux, Vy = w0 * nu0 * g0s * uy, Vz = w0 * nu0 * g0s * uz;
     R Ap = -lam[0] * n0, Am = R(0);
-    R Gx = 0, Gy = 0, Gz = 0;  // sum_p 2 w lam^- c_p
-    R nup[9], num[9];
+    R Gx = 0, Gy = 0, Gz = 0;  // force part of dJ/da
+    R ne[NP];                  // even non-equilibrium parts (MRT dJ/domega)
 #pragma unroll
-    for (int p = 0; p < 9; ++p) {
+    for (int p = 0; p < NP; ++p) {
         const int q = 2 * p + 1;
-        const R w = R(weight(q));
+        const R w = R(wq(QN, q));
+        const R cx = R(kC[q].x), cy = R(kC[q].y), cz = R(kC[q].z);
         const R lp = R(0.5) * (lam[q] + lam[q + 1]);
         const R lm = R(0.5) * (lam[q] - lam[q + 1]);
-        nup[p] = P.wp * lp;
-        num[p] = P.wm * lm;
+        if constexpr (!(MRT && QN == 19)) {
+            nup[p] = P.wp * lp;
+            num[p] = P.wm * lm;
+        }
         const R np = R(0.5) * (d[q] + d[q + 1]) - w * (drho + E[p]);
-        const R nm = R(0.5) * (d[q] - d[q + 1]) - w * (R(3) * cu[p]);
-        Ap -= R(2) * lp * np;
-        Am -= R(2) * lm * (nm + R(0.5) * P.fraw[p]);
+        R O = R(3) * cu[p];
+        if constexpr (CUBIC) O = O + O3[p];
+        const R nm = R(0.5) * (d[q] - d[q + 1]) - w * O;
         S0 += R(2) * w * nup[p];
         const R t2 = R(2) * w * nup[p], t6 = R(6) * w * num[p];
-        Vx += t2 * gE[p][0] + t6 * cxp[p];
-        Vy += t2 * gE[p][1] + t6 * cyp[p];
-        Vz += t2 * gE[p][2] + t6 * czp[p];
-        const R l2w = R(2) * w * lm;
-        Gx += l2w * cxp[p];
-        Gy += l2w * cyp[p];
-        Gz += l2w * czp[p];
+        Vx += t2 * gE[p][0] + t6 * cx;
+        Vy += t2 * gE[p][1] + t6 * cy;
+        Vz += t2 * gE[p][2] + t6 * cz;
+        if constexpr (CUBIC) {
+            const R tm = R(2) * w * num[p];
+            Vx += tm * gO3[p][0];
+            Vy += tm * gO3[p][1];
+            Vz += tm * gO3[p][2];
+        }
+        if constexpr (MRT && QN == 19) {
+            // force [lam_q - lam_qbar] . (I - K_o/2) F with F_p = 3 w c.a:
+            // d/da_b = 3 w c_b ((lam_q - lam_qbar) - nu-_p) per pair
+            ne[p] = np;
+            const R gf = R(3) * w * (R(2) * lm - num[p]);
+            Gx += gf * cx;
+            Gy += gf * cy;
+            Gz += gf * cz;
+        } else {
+            Ap -= R(2) * lp * np;
+            Am -= R(2) * lm * (nm + R(0.5) * P.fraw[p]);
+            const R l2w = R(2) * w * lm;
+            Gx += l2w * cx;
+            Gy += l2w * cy;
+            Gz += l2w * cz;
+        }
     }
-    acc[0] += (A)(Ap + Am * P.kappa);
-    const R fm = R(3) * (R(1) - R(0.5) * P.wm);
-    acc[1] += (A)(R(0.5) * Vx + fm * Gx);
-    acc[2] += (A)(R(0.5) * Vy + fm * Gy);
-    acc[3] += (A)(R(0.5) * Vz + fm * Gz);
+    if constexpr (MRT && QN == 19) {
+        // only the second-order moments' rate depends on omega:
+        // dJ/domega = -[lam_0, lam_q + lam_qbar] . (dK_e/domega) [n0, ne]
+        R acc0 = R(0);
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            R v = P.pe2[10 * i] * n0;
+#pragma unroll
+            for (int j = 0; j < 9; ++j) v += P.pe2[10 * i + j + 1] * ne[j];
+            const R li = i == 0 ? lam[0] : lam[2 * i - 1] + lam[2 * i];
+            acc0 -= li * v;
+        }
+        acc[0] += (A)acc0;
+        acc[1] += (A)(R(0.5) * Vx + Gx);
+        acc[2] += (A)(R(0.5) * Vy + Gy);
+        acc[3] += (A)(R(0.5) * Vz + Gz);
+    } else {
+        acc[0] += (A)(Ap + Am * P.kappa);
+        const R fm = R(3) * (R(1) - R(0.5) * P.wm);
+        acc[1] += (A)(R(0.5) * Vx + fm * Gx);
+        acc[2] += (A)(R(0.5) * Vy + fm * Gy);
+        acc[3] += (A)(R(0.5) * Vz + fm * Gz);
+    }
     lam[0] = lam[0] - nu0 + S0;
 #pragma unroll
-    for (int p = 0; p < 9; ++p) {
+    for (int p = 0; p < NP; ++p) {
         const int q = 2 * p + 1;
-        const R cv = cxp[p] * Vx + cyp[p] * Vy + czp[p] * Vz;
+        const R cv = R(kC[q].x) * Vx + R(kC[q].y) * Vy + R(kC[q].z) * Vz;
         lam[q] = lam[q] - (nup[p] + num[p]) + S0 + cv;
         lam[q + 1] = lam[q + 1] - (nup[p] - num[p]) + S0 - cv;
     }

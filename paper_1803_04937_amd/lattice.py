@@ -87,9 +87,9 @@ class Lattice:
         return torch.empty((self.q, self.qstride), dtype=self.storage_dtype, device=self.device)
 
     def new_adjoint(self, zero: bool = True) -> torch.Tensor:
-        """An adjoint field: tensor (19, qstride) of the adjoint dtype."""
+        """An adjoint field: tensor (Q, qstride) of the adjoint dtype."""
         f = torch.zeros if zero else torch.empty
-        return f((19, self.qstride), dtype=self.adjoint_dtype, device=self.device)
+        return f((self.q, self.qstride), dtype=self.adjoint_dtype, device=self.device)
 
     def state_view(self, buf: torch.Tensor) -> torch.Tensor:
         """(Q, nz, ny, nx) view of the cells of a state or adjoint buffer."""

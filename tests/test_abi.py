@@ -59,6 +59,7 @@ def test_layout_sizes(capi):
     assert capi.lbm_state_bytes(p64) == 19 * capi.lbm_qstride(p64) * 8
     p27 = capi.make_params(64, 64, 64, dtype=capi.LBM_F32, stencil=27)
     assert capi.lbm_state_bytes(p27) == 27 * capi.lbm_qstride(p27) * 4
+    assert capi.lbm_adjoint_bytes(p27) == 27 * capi.lbm_qstride(p27) * 4
 
 
 BAD = [

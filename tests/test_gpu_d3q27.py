@@ -81,14 +81,22 @@ def test_d3q27_256_f32_sampled():
     assert np.all(np.abs(got - want) <= reduced_bound(want, "f32", 1.0))
 
 
-def test_d3q27_has_no_adjoint():
+def test_d3q27_adjoint_field_and_compressible_refusal():
+    """The D3Q27 adjoint works on 27-array fields (its parity is in
+    test_gpu_adjoint_wide.py); the compressible form has no adjoint."""
     from paper_1803_04937_amd import LBMError, capi
     cfg, kw = case(8, 8, 8, stencil=27)
     lat = lattice(cfg, kw, np.zeros((3,) + cfg.shape), dtype="f32")
-    lam = torch.zeros((19, lat.qstride), dtype=torch.float32, device="cuda")
+    lam = lat.new_adjoint()
+    assert lam.shape == (27, lat.qstride)
+    lat.close()
+    cfg, kw = case(8, 8, 8, stencil=27, compressible=True)
+    lat = lattice(cfg, kw, np.zeros((3,) + cfg.shape), dtype="f32")
+    lam = lat.new_adjoint()
     with pytest.raises(LBMError) as e:
-        lat.adjoint_step(lat.state, lam, lam.clone())
+        lat.adjoint_step(lat.state, lam, lat.new_adjoint())
     assert e.value.status == capi.LBM_ESTATE
+    lat.close()
 
 
 def test_d3q27_duct_has_no_spurious_current():

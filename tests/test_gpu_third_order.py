@@ -3,7 +3,6 @@ construction of Sec. 3.2 carried to O(u^3)) against the oracle, which
 evaluates it by the moment-matching solve itself."""
 import numpy as np
 import pytest
-import torch
 
 import lbm_inputs
 import oracle
@@ -61,16 +60,6 @@ def test_third_order_reduced_precision_one_step(dtype):
     want = oracle.step(cfg, f_in, 1)
     ratio = np.abs(host(lat.get_pdfs()) - want) / reduced_bound(want, dtype, lat.scale)
     assert ratio.max() <= 1.0, ratio.max()
-
-
-def test_third_order_has_no_adjoint():
-    from paper_1803_04937_amd import LBMError, capi
-    cfg, kw = case(8, 8, 8, improved=2)
-    lat = lattice(cfg, kw, np.zeros((3,) + cfg.shape), dtype="f32")
-    lam = lat.new_adjoint()
-    with pytest.raises(LBMError) as e:
-        lat.adjoint_step(lat.state, lam, lat.new_adjoint())
-    assert e.value.status == capi.LBM_ESTATE
 
 
 def test_third_order_duct_has_no_spurious_current():

@@ -8,8 +8,9 @@ The arithmetic lives in ``oracle.c`` (plain C, FP64, OpenMP over z); this
 module only loads it with ctypes and marshals numpy arrays.  The exact-rational
 equilibrium construction of Sec. 3 lives in ``oracle.moment_matching``.
 
-Array conventions: PDFs are float64 arrays of shape (19, nz, ny, nx), x
-fastest; velocities (3, nz, ny, nx); densities and masks (nz, ny, nx).
+Array conventions: PDFs are float64 arrays of shape (Q, nz, ny, nx), Q = 19
+(D3Q19) or 27 (D3Q27), x fastest; velocities (3, nz, ny, nx); densities and
+masks (nz, ny, nx).
 """
 from __future__ import annotations
 
@@ -26,8 +27,6 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # The pin suite can be pointed at another build of oracle.c (a deliberately
 # broken copy, to show that the pins catch the mistake).
 _LIB_OVERRIDE = os.environ.get("LBM_ORACLE_LIB")
-
-NQ = 19
 
 
 def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:

@@ -1,4 +1,4 @@
-// C ABI of the D3Q19 stream-collide library: parameter validation, context
+// C ABI of the D3Q19 / D3Q27 stream-collide library: parameter validation, context
 // state, launch configuration and error reporting.  Kernels live in
 // forward.hip and adjoint.hip.
 #include <math.h>

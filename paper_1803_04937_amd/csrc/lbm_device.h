@@ -16,7 +16,6 @@
 
 namespace lbm {
 
-constexpr int Q = 19;         // D3Q19 (the adjoint is written for it)
 constexpr int kQMax = 27;     // D3Q27
 constexpr int kBlock = 256;   // threads per block for every cell kernel
 

@@ -92,10 +92,31 @@ def timed_forward(torch, lat, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def timed_adjoint(torch, lat, steps, warmup):
+    """Average duration (ms) of one adjoint step with parameter gradients,
+    linearised at the lattice's current state."""
+    lam = [lat.new_adjoint(), lat.new_adjoint()]
+    grad = torch.zeros(4, dtype=torch.float64, device=lat.device)
+    out = torch.zeros(4, dtype=torch.float64, device=lat.device)
+    lat.objective(0, lat.state, out, lam[0])
+    for i in range(warmup):
+        lat.adjoint_step(lat.state, lam[i % 2], lam[1 - i % 2], grad)
+    e0, e1 = _events(torch, 2)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(steps):
+        lat.adjoint_step(lat.state, lam[i % 2], lam[1 - i % 2], grad)
+    e1.record()
+    torch.cuda.synchronize()
+    if not torch.isfinite(grad).all():
+        raise RuntimeError("non-finite adjoint gradient")
+    return e0.elapsed_time(e1) / steps
+
+
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
@@ -237,6 +258,25 @@ def main():
             "time_ratio_vs_trt": round(msm / fwd_ms, 3)}
         lat2.close()
         del lat2
+        # adjoint of other configurations: bytes = Q (sizeof(state) + 2 sizeof(lam))
+        for name, kw, q, size in [
+                ("adj_f16s_I_trt", dict(dtype="f16s"), 19, 2 + 2 * 4),
+                ("adj_f64_I_trt", dict(dtype="f64"), 19, 3 * 8),
+                ("adj_f32_I_mrt", dict(dtype="f32", collision="mrt", mrt_omega3=1.6,
+                                       mrt_omega4=1.2), 19, 3 * 4),
+                ("adj_f32_I3_trt", dict(dtype="f32", equilibrium="improved3"), 19, 3 * 4),
+                ("adj_f32_d3q27_trt", dict(dtype="f32", stencil=27), 27, 3 * 4)]:
+            _log(f"extra {name}")
+            c = dict(common)
+            c.update(kw)
+            lat2 = Lattice(n, n, n, u=u0, **c)
+            ms = timed_adjoint(torch, lat2, 20, 3)
+            gbs = q * size * ncells / (ms * 1e-3) / 1e9
+            extras[name] = {"ms": round(ms, 5), "mlups": round(ncells / (ms * 1e-3) / 1e6, 1),
+                            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            lat2.close()
+            del lat2
+            torch.cuda.empty_cache()
     if copy_ms is not None:
         extras["copy_state_f32"] = {"ms": round(copy_ms, 5), "bytes": 2 * state_bytes,
                                     "GBs": round(2 * state_bytes / (copy_ms * 1e-3) / 1e9, 1)}

@@ -106,6 +106,14 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2, LBM_F16_SHIFTED = 3,
  * FP32 formats; the initial state and lbm_set_pdfs round to nearest. */
 enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
 
+/* Cache policy of the stream-collide kernels.  STREAM: non-temporal hints
+ * (each value is touched once per step; best when the data is far larger
+ * than the 256 MB last-level cache).  KEEP: ordinary cached accesses, so a
+ * lattice that fits the cache is served from it between steps.  AUTO: KEEP
+ * when one step touches at most 192 MiB (both buffers for two-grid, the one
+ * buffer for AA), STREAM otherwise.  Results are identical bit for bit. */
+enum { LBM_CACHE_AUTO = 0, LBM_CACHE_STREAM = 1, LBM_CACHE_KEEP = 2 };
+
 /* Streaming patterns.  TWO_GRID: pull from one buffer into another.  AA:
  * one buffer updated in place, alternating a step that reads and writes the
  * cell's own slots with a step that reads and writes the neighbours'. */
@@ -136,6 +144,7 @@ typedef struct {
     double mrt_omega4;        /* MRT rate of the fourth-order moments, (0, 2)     */
     int32_t rounding;         /* LBM_ROUND_NEAREST / LBM_ROUND_STOCHASTIC          */
     uint32_t seed;            /* key of the stochastic rounding                    */
+    int32_t cache_policy;     /* LBM_CACHE_AUTO / STREAM / KEEP                    */
 } lbm_params;
 
 /* Library version string. */

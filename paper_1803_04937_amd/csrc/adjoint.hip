@@ -41,17 +41,19 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
         if (GEN && g.solid && g.solid[idx]) {
 #pragma unroll
             for (int q = 0; q < QN; ++q)
-                st(lam_prev + q * g.qstride + idx, ld(lam_next + q * g.qstride + idx));
+                st<true>(lam_prev + q * g.qstride + idx, ld<true>(lam_next + q * g.qstride + idx));
         } else {
             const Hood h = make_hood(idx, g);
             R d[QN], lam[QN];
+            // one hint for every direction: plain unrolled loops suffice
+            constexpr bool HL = LBM_NT_ADJ_LOADS != 0, HS = LBM_NT_ADJ_STORES != 0;
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
                 bool fl;
                 const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
                 const typename S::T *p = state + (fl ? q : opp(q)) * g.qstride;
-                d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_adj(kC[q].x));
-                lam[q] = (R)ld(lam_next + q * g.qstride + idx);
+                d[q] = S::template load<HL>(p, fl ? c : idx, (R)wq(QN, q), P.inv_s);
+                lam[q] = (R)ld<HL>(lam_next + q * g.qstride + idx);
             }
             adjoint_cell<R, EQ, QN, MRT>(d, lam, P, acc);
 #pragma unroll
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
                 bool fl;
                 const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
                 L *p = lam_prev + (fl ? q : opp(q)) * g.qstride;
-                st(p + (fl ? c : idx), (L)lam[q], nt_store(kC[q].x));
+                st<HS>(p + (fl ? c : idx), (L)lam[q]);
             }
         }
     }

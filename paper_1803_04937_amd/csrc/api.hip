@@ -18,6 +18,7 @@ struct lbm_ctx {
     lbm_params p;
     Geom g;
     bool gen;          // walls or solid cells present
+    bool nt;           // stream-collide with non-temporal hints (cache policy)
     void *buf[2];
     int cur;           // two-grid: index of the buffer holding the state
     hipStream_t stream;
@@ -143,6 +144,11 @@ static int validate(const lbm_params *p, std::string &why) {
             why = "accel must be finite";
             return LBM_EINVAL;
         }
+    if (p->cache_policy != LBM_CACHE_AUTO && p->cache_policy != LBM_CACHE_STREAM &&
+        p->cache_policy != LBM_CACHE_KEEP) {
+        why = "cache_policy must be LBM_CACHE_AUTO, LBM_CACHE_STREAM or LBM_CACHE_KEEP";
+        return LBM_EINVAL;
+    }
     if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC) {
         why = "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC";
         return LBM_EINVAL;
@@ -394,6 +400,13 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
     g.qstride = qstride_of(p);
     g.solid = solid;
     c->gen = solid != nullptr || !(p->periodic[0] && p->periodic[1] && p->periodic[2]);
+    {
+        size_t state_bytes = 0;
+        lbm_state_bytes(p, &state_bytes);
+        const size_t touched = (p->pattern == LBM_TWO_GRID ? 2 : 1) * state_bytes;
+        c->nt = p->cache_policy == LBM_CACHE_STREAM ||
+                (p->cache_policy == LBM_CACHE_AUTO && touched > kCacheResidentBytes);
+    }
     // host self-check of the division constants on the extreme values
     const uint32_t probes[4] = {0u, g.nx - 1, g.nx, g.ncells - 1};
     for (uint32_t v : probes)
@@ -462,15 +475,17 @@ extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
         hipError_t e;
         if (c->p.pattern == LBM_TWO_GRID) {
             e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                               c->p.collision == LBM_MRT, c->gen, sr(c), step_key(c->p.seed, c->t),
-                               c->coll, c->buf[c->cur], c->buf[1 - c->cur], c->stream);
+                               c->p.collision == LBM_MRT, c->gen, sr(c), c->nt,
+                               step_key(c->p.seed, c->t), c->coll, c->buf[c->cur],
+                               c->buf[1 - c->cur], c->stream);
             if (e == hipSuccess) c->cur ^= 1;
         } else {
             // even step count: the state is in local layout, so the next step
             // is a neighbour step; odd: a local step.
             e = launch_step_aa(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                               c->p.collision == LBM_MRT, c->gen, sr(c), step_key(c->p.seed, c->t),
-                               (c->t & 1) == 0, c->coll, c->buf[0], c->stream);
+                               c->p.collision == LBM_MRT, c->gen, sr(c), c->nt,
+                               step_key(c->p.seed, c->t), (c->t & 1) == 0, c->coll, c->buf[0],
+                               c->stream);
         }
         if (e != hipSuccess) return hip_fail(c, e, "step");
         c->t += 1;
@@ -483,8 +498,8 @@ extern "C" int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst, int64_
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct buffers");
     if (t < 0) return fail(c, LBM_EINVAL, "t must be >= 0");
     hipError_t e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                                  c->p.collision == LBM_MRT, c->gen, sr(c), step_key(c->p.seed, t),
-                                  c->coll, src, dst, c->stream);
+                                  c->p.collision == LBM_MRT, c->gen, sr(c), c->nt,
+                                  step_key(c->p.seed, t), c->coll, src, dst, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "stream_collide");
     return LBM_OK;
 }

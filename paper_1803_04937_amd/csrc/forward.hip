@@ -120,10 +120,18 @@ __global__ __launch_bounds__(kBlock) void k_init_maxdev(Geom g, int compressible
     block_reduce<1, true>(m, partials + blockIdx.x);
 }
 
+// Memory hints of the stream-collide kernels for direction q (x component
+// cx): with NT (the streaming cache policy) as set by LBM_NT_FWD_LOADS and
+// LBM_NT_FWD_STORES, none otherwise.
+template <bool NT>
+__host__ __device__ constexpr bool fwd_load_hint(int cx) { return NT && hint_of(LBM_NT_FWD_LOADS, cx); }
+template <bool NT>
+__host__ __device__ constexpr bool fwd_store_hint(int cx) { return NT && hint_of(LBM_NT_FWD_STORES, cx); }
+
 // ---------------------------------------------------------------------------
 // Two-grid pull step: dst[q][x] = f*_q(x) from src.
 // ---------------------------------------------------------------------------
-template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR>
+template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<DT>::R> P,
                                                     const typename Store<DT>::T *__restrict__ src,
                                                     typename Store<DT>::T *__restrict__ dst,
@@ -135,22 +143,23 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
     if (GEN && is_solid(g, idx)) return;
     const Hood h = make_hood(idx, g);
     R d[QN];
-#pragma unroll
-    for (int q = 0; q < QN; ++q) {
+    static_for<QN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
         const typename S::T *p = src + (fl ? q : opp(q)) * g.qstride;
-        d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_fwd(kC[q].x));
-    }
+        d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? c : idx, (R)wq(QN, q), P.inv_s);
+    });
     collide<R, EQ, QN, MRT>(d, P);
     SrBits rb{SR ? mix32(idx ^ key) : 0u};
-#pragma unroll
-    for (int q = 0; q < QN; ++q) {
+    static_for<QN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr bool H = fwd_store_hint<NT>(0);   // aligned stores
         if constexpr (SR)
-            store_sr<DT>(dst + q * g.qstride, idx, d[q], P.s, rb.next(q));
+            store_sr<DT, H>(dst + q * g.qstride, idx, d[q], P.s, rb.next(q));
         else
-            S::store(dst + q * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
-    }
+            S::template store<H>(dst + q * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -162,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
 // Every slot a cell reads is written by the same cell, so the in-place
 // update is race-free.
 // ---------------------------------------------------------------------------
-template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR>
+template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Store<DT>::R> P,
                                                        typename Store<DT>::T *A, uint32_t key) {
     using S = Store<DT>;
@@ -172,28 +181,29 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
     if (GEN && is_solid(g, idx)) return;
     const Hood h = make_hood(idx, g);
     R d[QN];
-#pragma unroll
-    for (int q = 0; q < QN; ++q) {
+    static_for<QN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
         const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
-        d[q] = S::load(p, fl ? c : idx, (R)wq(QN, q), P.inv_s, nt_load_fwd(kC[q].x));
-    }
+        d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? c : idx, (R)wq(QN, q), P.inv_s);
+    });
     collide<R, EQ, QN, MRT>(d, P);
     SrBits rb{SR ? mix32(idx ^ key) : 0u};
-#pragma unroll
-    for (int q = 0; q < QN; ++q) {
+    static_for<QN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr bool H = fwd_store_hint<NT>(kC[q].x);
         bool fl;
         const uint32_t c = hood_cell<GEN>(h, g, q, +1, fl);
         typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
         if constexpr (SR)
-            store_sr<DT>(p, fl ? c : idx, d[q], P.s, rb.next(q), nt_store(kC[q].x));
+            store_sr<DT, H>(p, fl ? c : idx, d[q], P.s, rb.next(q));
         else
-            S::store(p, fl ? c : idx, d[q], (R)wq(QN, q), P.s, nt_store(kC[q].x));
-    }
+            S::template store<H>(p, fl ? c : idx, d[q], (R)wq(QN, q), P.s);
+    });
 }
 
-template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR>
+template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename Store<DT>::R> P,
                                                         typename Store<DT>::T *A, uint32_t key) {
     using S = Store<DT>;
@@ -202,17 +212,21 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename St
     if (idx >= g.ncells) return;
     if (GEN && is_solid(g, idx)) return;
     R d[QN];
-#pragma unroll
-    for (int q = 0; q < QN; ++q) d[q] = S::load(A + q * g.qstride, idx, (R)wq(QN, q), P.inv_s);
+    static_for<QN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        d[q] = S::template load<fwd_load_hint<NT>(0)>(A + q * g.qstride, idx, (R)wq(QN, q),
+                                                      P.inv_s);
+    });
     collide<R, EQ, QN, MRT>(d, P);
     SrBits rb{SR ? mix32(idx ^ key) : 0u};
-#pragma unroll
-    for (int q = 0; q < QN; ++q) {
+    static_for<QN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr bool H = fwd_store_hint<NT>(0);
         if constexpr (SR)
-            store_sr<DT>(A + opp(q) * g.qstride, idx, d[q], P.s, rb.next(q));
+            store_sr<DT, H>(A + opp(q) * g.qstride, idx, d[q], P.s, rb.next(q));
         else
-            S::store(A + opp(q) * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
-    }
+            S::template store<H>(A + opp(q) * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -408,6 +422,11 @@ __global__ __launch_bounds__(kBlock) void k_copy(const u32x4 *__restrict__ src,
 // ---------------------------------------------------------------------------
 
 
+// Non-temporal hints on (streaming) or off (cache-resident lattices).
+#define LBM_DISPATCH_NT(BODY)                             \
+    if (nt) { constexpr bool NT = true; BODY; }           \
+    else { constexpr bool NT = false; BODY; }
+
 // Stochastic rounding exists for the 16-bit formats only.
 #define LBM_DISPATCH_SR(BODY)                                                       \
     if constexpr (DT == LBM_F16_SHIFTED || DT == LBM_BF16_SHIFTED) {                \
@@ -440,30 +459,32 @@ hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, c
 }
 
 hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
-                          bool sr, uint32_t key, const CollBoth &P, const void *src, void *dst,
-                          hipStream_t st) {
+                          bool sr, bool nt, uint32_t key, const CollBoth &P, const void *src,
+                          void *dst, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(LBM_DISPATCH_SR({
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(
+        LBM_DISPATCH_SR(LBM_DISPATCH_NT({
         using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN, MRT, SR>), grid, block, LBM_STEP_LDS_BYTES,
-                           st, g, pick<DT>(P), (const T *)src, (T *)dst, key);
-    })))));
+        hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
+                           LBM_STEP_LDS_BYTES, st, g, pick<DT>(P), (const T *)src, (T *)dst, key);
+    }))))));
     return hipGetLastError();
 }
 
 hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
-                          bool sr, uint32_t key, bool neighbor, const CollBoth &P, void *A,
-                          hipStream_t st) {
+                          bool sr, bool nt, uint32_t key, bool neighbor, const CollBoth &P,
+                          void *A, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(LBM_DISPATCH_SR({
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(
+        LBM_DISPATCH_SR(LBM_DISPATCH_NT({
         using T = typename Store<DT>::T;
         if (neighbor)
-            hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN, MRT, SR>), grid, block,
+            hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
                                LBM_STEP_LDS_BYTES, st, g, pick<DT>(P), (T *)A, key);
         else
-            hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN, MRT, SR>), grid, block,
+            hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
                                LBM_STEP_LDS_BYTES, st, g, pick<DT>(P), (T *)A, key);
-    })))));
+    }))))));
     return hipGetLastError();
 }
 

@@ -49,13 +49,14 @@ hipError_t launch_init(const Geom &g, int qn, int dtype, int eq, int compressibl
                        hipStream_t st);
 hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, const double *rho,
                               const double *u, const Scratch &sc, hipStream_t st);
-// sr: stochastic rounding of the 16-bit stores with the step key `key`.
+// sr: stochastic rounding of the 16-bit stores with the step key `key`;
+// nt: non-temporal hints (false: every access cached).
 hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
-                          bool sr, uint32_t key, const CollBoth &P, const void *src, void *dst,
-                          hipStream_t st);
+                          bool sr, bool nt, uint32_t key, const CollBoth &P, const void *src,
+                          void *dst, hipStream_t st);
 hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
-                          bool sr, uint32_t key, bool neighbor, const CollBoth &P, void *A,
-                          hipStream_t st);
+                          bool sr, bool nt, uint32_t key, bool neighbor, const CollBoth &P,
+                          void *A, hipStream_t st);
 hipError_t launch_get(const Geom &g, int qn, int dtype, Layout layout, double inv_s, const void *A,
                       double *out, hipStream_t st);
 hipError_t launch_sample(const Geom &g, int qn, int dtype, Layout layout, double inv_s,

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "lbm.h"
 
 namespace lbm {
@@ -47,22 +49,40 @@ __host__ __device__ constexpr double wq(int qn, int q) {
 
 // ---------------------------------------------------------------------------
 // Streaming memory access.  Every PDF and adjoint value is read once and
-// written once per step, so accesses carry the non-temporal hint (nt).  The
-// callers pass nt = false for x-shifted accesses when the hint would evict
-// the cache lines that neighbouring waves of the same row still need.
+// written once per step, so accesses may carry the non-temporal hint (NT).
+// The hint is a template parameter: a run-time choice between a hinted and a
+// plain access of the same address is merged by the optimiser into one plain
+// access (the hint is lost before the direction loops are unrolled), so each
+// instantiation below performs one kind of access only.  Where the hint
+// depends on the direction, callers branch between two instantiations on a
+// condition that unrolling makes constant.
 // ---------------------------------------------------------------------------
-// Measured on MI355X at 256^3 FP32: the forward pull is faster (+2 %) with
-// ordinary loads for its x-shifted directions, the adjoint (which also
-// streams lam) is faster (+6 %) with the hint on every load.
-#ifndef LBM_NT_FWD_SHIFTED_LOADS
-#define LBM_NT_FWD_SHIFTED_LOADS 0
+// Hint modes per kernel role (build-time tuning): 0 none, 1 only the
+// directions with c_x = 0 (aligned in memory), 2 all; the adjoint takes
+// 0 or 2.  Measured on MI355X at 256^3: forward loads 1 is best (all loads
+// hinted evict lines that the x-neighbours' waves still read; none leaves
+// the stream-collide output's lines competing with the next kernel), the
+// adjoint is best with every access hinted (aligned-only stores cost the
+// following forward step 12 %).  With the cached policy (NT = false) the
+// stream-collide kernels take no hint at all.
+#ifndef LBM_NT_FWD_LOADS
+#define LBM_NT_FWD_LOADS 1
 #endif
-#ifndef LBM_NT_ADJ_SHIFTED_LOADS
-#define LBM_NT_ADJ_SHIFTED_LOADS 1
+#ifndef LBM_NT_FWD_STORES
+#define LBM_NT_FWD_STORES 2
 #endif
-#ifndef LBM_NT_SHIFTED_STORES
-#define LBM_NT_SHIFTED_STORES 1
+#ifndef LBM_NT_ADJ_LOADS
+#define LBM_NT_ADJ_LOADS 2
 #endif
+#ifndef LBM_NT_ADJ_STORES
+#define LBM_NT_ADJ_STORES 2
+#endif
+__host__ __device__ constexpr bool hint_of(int mode, int cx) { return mode == 2 || (mode == 1 && cx == 0); }
+// The hint pays only when the data does not fit the 256 MB last-level cache:
+// the stream-collide kernels take NT = false (every access cached) for
+// lattices whose step touches at most kCacheResidentBytes, which are then
+// served from that cache between steps (10-21 % faster at 64^3-128^3).
+constexpr size_t kCacheResidentBytes = size_t(192) << 20;
 // Occupancy (build-time tuning).  LBM_STEP_LDS_BYTES > 0 reserves that much
 // dynamic LDS per stream-collide block, which caps the resident blocks per
 // CU at floor(160 KiB / bytes) (one 256-thread block = one wave per SIMD).
@@ -88,41 +108,38 @@ __host__ __device__ constexpr double wq(int qn, int q) {
 #else
 #define LBM_ADJ_OCCUPANCY
 #endif
-constexpr bool kNtShiftedLoadsForward = LBM_NT_FWD_SHIFTED_LOADS;
-constexpr bool kNtShiftedLoadsAdjoint = LBM_NT_ADJ_SHIFTED_LOADS;
-constexpr bool kNtShiftedStores = LBM_NT_SHIFTED_STORES;
 
-template <typename T>
-__device__ __forceinline__ T ld(const T *p, bool nt = true) {
-    return nt ? __builtin_nontemporal_load(p) : *p;
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
-template <typename T>
-__device__ __forceinline__ void st(T *p, T v, bool nt = true) {
-    if (nt)
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T *p, T v) {
+    if constexpr (NT)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
 }
-__device__ __forceinline__ _Float16 ld(const _Float16 *p, bool nt = true) {
-    const uint16_t *u = (const uint16_t *)p;
-    return __builtin_bit_cast(_Float16, nt ? __builtin_nontemporal_load(u) : *u);
+// 16-bit storage goes through its bit pattern.
+template <bool NT>
+__device__ __forceinline__ _Float16 ld(const _Float16 *p) {
+    return __builtin_bit_cast(_Float16, ld<NT>((const uint16_t *)p));
 }
-__device__ __forceinline__ void st(_Float16 *p, _Float16 v, bool nt = true) {
-    st((uint16_t *)p, __builtin_bit_cast(uint16_t, v), nt);
+template <bool NT>
+__device__ __forceinline__ void st(_Float16 *p, _Float16 v) {
+    st<NT>((uint16_t *)p, __builtin_bit_cast(uint16_t, v));
 }
-__device__ __forceinline__ __bf16 ld(const __bf16 *p, bool nt = true) {
-    const uint16_t *u = (const uint16_t *)p;
-    return __builtin_bit_cast(__bf16, nt ? __builtin_nontemporal_load(u) : *u);
+template <bool NT>
+__device__ __forceinline__ __bf16 ld(const __bf16 *p) {
+    return __builtin_bit_cast(__bf16, ld<NT>((const uint16_t *)p));
 }
-__device__ __forceinline__ void st(__bf16 *p, __bf16 v, bool nt = true) {
-    st((uint16_t *)p, __builtin_bit_cast(uint16_t, v), nt);
+template <bool NT>
+__device__ __forceinline__ void st(__bf16 *p, __bf16 v) {
+    st<NT>((uint16_t *)p, __builtin_bit_cast(uint16_t, v));
 }
-
-// Whether the access of direction q at x - c_q (or x + c_q) keeps the
-// non-temporal hint.
-__host__ __device__ constexpr bool nt_load_fwd(int cx) { return cx == 0 || kNtShiftedLoadsForward; }
-__host__ __device__ constexpr bool nt_load_adj(int cx) { return cx == 0 || kNtShiftedLoadsAdjoint; }
-__host__ __device__ constexpr bool nt_store(int cx) { return cx == 0 || kNtShiftedStores; }
 
 // ---------------------------------------------------------------------------
 // Storage formats.  load() returns d = f - w in the compute type R; store()
@@ -131,73 +148,97 @@ __host__ __device__ constexpr bool nt_store(int cx) { return cx == 0 || kNtShift
 template <int DT>
 struct Store;
 
+// Store<DT>: load returns d = f - w (R precision), store takes d; NT selects
+// the non-temporal hint.  load_f / store_f move raw f (FP64 and FP32 only).
 template <>
 struct Store<LBM_F64> {
     using T = double;
     using R = double;
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R, bool nt = true) {
-        return ld(p + i, nt) - w;
+    template <bool NT = true>
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) {
+        return ld<NT>(p + i) - w;
     }
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R, bool nt = true) {
-        st(p + i, (T)(d + w), nt);
+    template <bool NT = true>
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) {
+        st<NT>(p + i, (T)(d + w));
     }
     static __device__ __forceinline__ double load_f(const T *p, uint32_t i, double, double) {
-        return ld(p + i);
+        return ld<true>(p + i);
     }
     static __device__ __forceinline__ void store_f(T *p, uint32_t i, double f, double, double) {
-        st(p + i, f);
+        st<true>(p + i, f);
     }
 };
 template <>
 struct Store<LBM_F32> {
     using T = float;
     using R = float;
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R, bool nt = true) {
-        return ld(p + i, nt) - w;
+    template <bool NT = true>
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) {
+        return ld<NT>(p + i) - w;
     }
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R, bool nt = true) {
-        st(p + i, (T)(d + w), nt);
+    template <bool NT = true>
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) {
+        st<NT>(p + i, (T)(d + w));
     }
     static __device__ __forceinline__ double load_f(const T *p, uint32_t i, double, double) {
-        return ld(p + i);
+        return ld<true>(p + i);
     }
     static __device__ __forceinline__ void store_f(T *p, uint32_t i, double f, double, double) {
-        st(p + i, (float)f);
+        st<true>(p + i, (float)f);
     }
 };
 template <>
 struct Store<LBM_F32_SHIFTED> {
     using T = float;
     using R = float;
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R, bool nt = true) {
-        return ld(p + i, nt);
+    template <bool NT = true>
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R) {
+        return ld<NT>(p + i);
     }
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R, bool nt = true) {
-        st(p + i, d, nt);
+    template <bool NT = true>
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R) {
+        st<NT>(p + i, d);
     }
 };
 template <>
 struct Store<LBM_F16_SHIFTED> {
     using T = _Float16;
     using R = float;
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s, bool nt = true) {
-        return static_cast<float>(ld(p + i, nt)) * inv_s;
+    template <bool NT = true>
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s) {
+        return static_cast<float>(ld<NT>(p + i)) * inv_s;
     }
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s, bool nt = true) {
-        st(p + i, static_cast<_Float16>(d * s), nt);  // round to nearest even
+    template <bool NT = true>
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s) {
+        st<NT>(p + i, static_cast<_Float16>(d * s));  // round to nearest even
     }
 };
 template <>
 struct Store<LBM_BF16_SHIFTED> {
     using T = __bf16;
     using R = float;
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s, bool nt = true) {
-        return static_cast<float>(ld(p + i, nt)) * inv_s;
+    template <bool NT = true>
+    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s) {
+        return static_cast<float>(ld<NT>(p + i)) * inv_s;
     }
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s, bool nt = true) {
-        st(p + i, static_cast<__bf16>(d * s), nt);  // round to nearest even
+    template <bool NT = true>
+    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s) {
+        st<NT>(p + i, static_cast<__bf16>(d * s));  // round to nearest even
     }
 };
+
+// Compile-time loop over directions: f(std::integral_constant<int, q>) for
+// q = 0 .. N-1, so that per-direction template arguments (memory hints) are
+// constants.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // ---------------------------------------------------------------------------
 // Stochastic rounding of the 16-bit formats.  The random bits of the value
@@ -250,13 +291,13 @@ __device__ __forceinline__ float sr_truncate(float v, uint32_t r) {
     return __uint_as_float(b);
 }
 
-template <int DT>
+template <int DT, bool NT = true>
 __device__ __forceinline__ void store_sr(typename Store<DT>::T *p, uint32_t i, float d, float s,
-                                         uint32_t r, bool nt = true) {
+                                         uint32_t r) {
     if constexpr (DT == LBM_F16_SHIFTED)
-        st(p + i, static_cast<_Float16>(sr_truncate<13>(d * s, r)), nt);
+        st<NT>(p + i, static_cast<_Float16>(sr_truncate<13>(d * s, r)));
     else if constexpr (DT == LBM_BF16_SHIFTED)
-        st(p + i, static_cast<__bf16>(sr_truncate<16>(d * s, r)), nt);
+        st<NT>(p + i, static_cast<__bf16>(sr_truncate<16>(d * s, r)));
 }
 
 // Canonical (FP64) access: f = w + d.  The raw formats override these with

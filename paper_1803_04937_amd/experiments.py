@@ -16,8 +16,11 @@ Also here: a flow driven from rest by a small body force in every storage
 type, which measures how the rounding of the stored f - w treats a per-step
 force increment near its half-ulp (`driven_flow`).
 
+And the forward throughput against the lattice size (`size_sweep`).
+
 Usage: python -m paper_1803_04937_amd.experiments [--dtype f64] [--sizes 15,25,45]
        python -m paper_1803_04937_amd.experiments --driven-flow
+       python -m paper_1803_04937_amd.experiments --size-sweep
 """
 from __future__ import annotations
 
@@ -119,6 +122,42 @@ def driven_flow(dtype: str, shape=(32, 32, 32), walls: bool = False, g: float = 
             "omega": omega, "scale": scale, "rows": rows}
 
 
+def size_sweep(sizes=(16, 32, 64, 96, 128, 160, 192, 256, 384), dtypes=("f32", "f16s"),
+               policies=("auto",), min_updates: float = 4e9, device=None) -> list:
+    """Forward throughput of the periodic D3Q19-I TRT update against the
+    lattice size n^3: the launch-latency regime of small lattices, the regime
+    where the two state buffers fit the last-level cache, and the HBM
+    regime.  Each point times enough steps for about `min_updates` cell
+    updates (at least 50 steps)."""
+    import lbm_inputs
+    rows = []
+    for dt, n, policy in ((dt, n, pol) for dt in dtypes for n in sizes for pol in policies):
+        u0 = torch.as_tensor(lbm_inputs.shear_waves((n, n, n), seed=1, amax=0.03))
+        lat = Lattice(n, n, n, u=u0, equilibrium="improved", collision="trt", omega=1.8,
+                      dtype=dt, cache_policy=policy, device=device)
+        steps = max(50, int(min_updates / n ** 3))
+        lat.step(10)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        lat.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        size = {"f64": 8, "f32": 4, "f32s": 4, "f16s": 2, "bf16s": 2}[dt]
+        state_mb = 2 * 19 * size * n ** 3 / 1e6
+        rows.append({"dtype": dt, "n": n, "policy": policy, "steps": steps,
+                     "us_per_step": round(ms * 1e3, 2),
+                     "glups": round(n ** 3 / (ms * 1e-3) / 1e9, 2),
+                     "GBs": round(2 * 19 * size * n ** 3 / (ms * 1e-3) / 1e9, 1),
+                     "two_states_MB": round(state_mb, 1)})
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dtype", default="f64")
@@ -129,7 +168,13 @@ def main():
                     help="also sweep Lambda^2 at this D for the standard equilibrium")
     ap.add_argument("--driven-flow", action="store_true",
                     help="only run the small-force driven flow in every storage type")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="only run the forward throughput sweep over lattice sizes")
     a = ap.parse_args()
+    if a.size_sweep:
+        for row in size_sweep(policies=("stream", "keep")):
+            print(json.dumps(row), flush=True)
+        return
     if a.driven_flow:
         runs = [(dt, "nearest") for dt in ("f64", "f32", "f32s", "f16s", "bf16s")]
         runs += [("f16s", "stochastic"), ("bf16s", "stochastic")]

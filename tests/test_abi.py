@@ -86,6 +86,7 @@ BAD = [
     (dict(collision=2, mrt_omega4=2.5), "mrt_omega4"),
     (dict(collision=3), "collision"),
     (dict(rounding=2), "rounding"),
+    (dict(cache_policy=3), "cache_policy"),
 ]
 
 

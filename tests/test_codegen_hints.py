@@ -1,0 +1,69 @@
+"""The memory hints reach the machine code (CPU only: hipcc cross-compiles).
+
+A run-time choice between a non-temporal and a plain access of one address is
+merged by the optimiser into a plain access, silently; the kernels therefore
+take their hints as template parameters.  This test compiles the kernel
+sources to gfx950 assembly with the library's own flags and counts the `nt`
+cache-policy bits of every stream-collide and adjoint instantiation:
+  streaming forward (NT = 1): the 9 loads with c_x = 0 (all loads in the AA
+      local step, which reads its own slots) and every store;
+  cached forward (NT = 0): none;
+  adjoint: every PDF and lambda load and every lambda store.
+"""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1803_04937_amd import build as B
+
+KERNEL = re.compile(r'^(_ZN3lbm\d+(k_step_tg|k_step_aa_nb|k_step_aa_loc|k_adjoint)I\S*?)'
+                    r'EEEvNS\S*:\s', re.M)
+
+
+def _assembly(src, tmp_path):
+    out = tmp_path / (src + ".s")
+    cmd = [B.HIPCC, *B.FLAGS, "--cuda-device-only", "-S", os.path.join(B.CSRC, src), "-o",
+           str(out)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return out.read_text()
+
+
+def _counts(asm):
+    for m in KERNEL.finditer(asm):
+        body = asm[m.end():asm.index(".Lfunc_end", m.end())]
+        loads = re.findall(r"global_load\S*[^\n]*", body)
+        stores = re.findall(r"global_store\S*[^\n]*", body)
+        yield (m.group(1), m.group(2), sum(bool(re.search(r"\bnt\b", x)) for x in loads),
+               sum(bool(re.search(r"\bnt\b", x)) for x in stores), len(loads), len(stores))
+
+
+def test_forward_hints(tmp_path):
+    asm = _assembly("forward.hip", tmp_path)
+    seen = 0
+    for name, kind, nl, ns, _, _ in _counts(asm):
+        qn, nt = re.search(r"ILi(\d+)E.*ELb([01])$", name).groups()
+        qn = int(qn)
+        want_l = 0 if nt == "0" else (qn if kind == "k_step_aa_loc" else 9)
+        want_s = 0 if nt == "0" else qn
+        assert (nl, ns) == (want_l, want_s), (name, nl, ns)
+        seen += 1
+    assert seen > 500, seen
+
+
+def test_adjoint_hints(tmp_path):
+    asm = _assembly("adjoint.hip", tmp_path)
+    seen = 0
+    for name, _, nl, ns, n_loads, _ in _counts(asm):
+        qn = int(re.search(r"ILi(\d+)E", name).group(1))
+        gen = re.search(r"ILi\d+ELi\dELi\dELi\dELb([01])", name).group(1) == "1"
+        # every PDF load and every lambda load / store is hinted (without
+        # gradients the rest population's PDF is dead: 2 Q - 1 loads); kernels
+        # with walls or masks also read the mask and copy lambda through
+        # solid cells
+        assert nl >= 2 * qn - 1 and ns >= qn, (name, nl, ns)
+        if not gen:
+            assert nl == n_loads and ns == qn, (name, nl, n_loads, ns)
+        seen += 1
+    assert seen > 100, seen

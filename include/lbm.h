@@ -106,12 +106,14 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2, LBM_F16_SHIFTED = 3,
  * FP32 formats; the initial state and lbm_set_pdfs round to nearest. */
 enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
 
-/* Cache policy of the stream-collide kernels.  STREAM: non-temporal hints
- * (each value is touched once per step; best when the data is far larger
- * than the 256 MB last-level cache).  KEEP: ordinary cached accesses, so a
- * lattice that fits the cache is served from it between steps.  AUTO: KEEP
- * when one step touches at most 192 MiB (both buffers for two-grid, the one
- * buffer for AA), STREAM otherwise.  Results are identical bit for bit. */
+/* Cache policy of the stream-collide and adjoint kernels.  STREAM:
+ * non-temporal hints (each value is touched once per step; best when the
+ * data is far larger than the 256 MB last-level cache).  KEEP: ordinary
+ * cached accesses, so a lattice that fits the cache is served from it
+ * between steps.  AUTO: KEEP for a kernel when one of its steps touches at
+ * most 240 MiB (stream-collide: both buffers for two-grid, the one buffer
+ * for AA; adjoint: the state and two adjoint fields), STREAM otherwise.
+ * Results are identical bit for bit. */
 enum { LBM_CACHE_AUTO = 0, LBM_CACHE_STREAM = 1, LBM_CACHE_KEEP = 2 };
 
 /* Streaming patterns.  TWO_GRID: pull from one buffer into another.  AA:

@@ -27,7 +27,7 @@ struct Lam<LBM_F32> {
 // lam_t[rbar][x] when x - c_r is a wall or solid).  Each f_t slot is read by
 // exactly one cell in the forward step, so each lam_t slot is written
 // exactly once.  Solid cells copy lam through.
-template <int QN, int DT, int LT, int EQ, bool GEN, bool MRT, bool GRAD>
+template <int QN, int DT, int LT, int EQ, bool GEN, bool MRT, bool GRAD, bool NT>
 __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     Geom g, Coll<typename Store<DT>::R> P, const typename Store<DT>::T *__restrict__ state,
     const typename Lam<LT>::T *__restrict__ lam_next, typename Lam<LT>::T *__restrict__ lam_prev,
@@ -41,12 +41,12 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
         if (GEN && g.solid && g.solid[idx]) {
 #pragma unroll
             for (int q = 0; q < QN; ++q)
-                st<true>(lam_prev + q * g.qstride + idx, ld<true>(lam_next + q * g.qstride + idx));
+                st<NT>(lam_prev + q * g.qstride + idx, ld<NT>(lam_next + q * g.qstride + idx));
         } else {
             const Hood h = make_hood(idx, g);
             R d[QN], lam[QN];
             // one hint for every direction: plain unrolled loops suffice
-            constexpr bool HL = LBM_NT_ADJ_LOADS != 0, HS = LBM_NT_ADJ_STORES != 0;
+            constexpr bool HL = NT && LBM_NT_ADJ_LOADS != 0, HS = NT && LBM_NT_ADJ_STORES != 0;
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
                 bool fl;
@@ -174,24 +174,25 @@ __global__ __launch_bounds__(kBlock) void k_init_vjp(Geom g, const double *__res
 #define LBM_LT_OF(DT) ((DT) == LBM_F64 ? LBM_F64 : LBM_F32)
 
 hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, bool mrt, bool gen,
-                          const CollBoth &P, const void *state, const void *lam_next,
+                          bool nt, const CollBoth &P, const void *state, const void *lam_next,
                           void *lam_prev, double *grad, const Scratch &sc, hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
     const bool want = grad != nullptr;
     if (ltype != (dtype == LBM_F64 ? LBM_F64 : LBM_F32)) return hipErrorInvalidValue;
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT({
+    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(
+        LBM_DISPATCH_NT({
         constexpr int LT = LBM_LT_OF(DT);
         using T = typename Store<DT>::T;
         using L = typename Lam<LT>::T;
         if (want)
-            hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, true>), grid, block,
+            hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, true, NT>), grid, block,
                                LBM_ADJ_LDS_BYTES, st, g, pick<DT>(P), (const T *)state,
                                (const L *)lam_next, (L *)lam_prev, sc.partials);
         else
-            hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, false>), grid, block,
+            hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, false, NT>), grid, block,
                                LBM_ADJ_LDS_BYTES, st, g, pick<DT>(P), (const T *)state,
                                (const L *)lam_next, (L *)lam_prev, sc.partials);
-    }))));
+    })))));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !want) return e;
     return launch_finalize(sc, cell_blocks(g), 4, 0, grad, true, st);

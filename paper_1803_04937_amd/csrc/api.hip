@@ -19,6 +19,7 @@ struct lbm_ctx {
     Geom g;
     bool gen;          // walls or solid cells present
     bool nt;           // stream-collide with non-temporal hints (cache policy)
+    bool adj_nt;       // adjoint with non-temporal hints
     void *buf[2];
     int cur;           // two-grid: index of the buffer holding the state
     hipStream_t stream;
@@ -403,9 +404,14 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
     {
         size_t state_bytes = 0;
         lbm_state_bytes(p, &state_bytes);
+        size_t adj_bytes = 0;
+        lbm_adjoint_bytes(p, &adj_bytes);
         const size_t touched = (p->pattern == LBM_TWO_GRID ? 2 : 1) * state_bytes;
+        const size_t touched_adj = state_bytes + 2 * adj_bytes;   // f_t, lam_next, lam_prev
         c->nt = p->cache_policy == LBM_CACHE_STREAM ||
                 (p->cache_policy == LBM_CACHE_AUTO && touched > kCacheResidentBytes);
+        c->adj_nt = p->cache_policy == LBM_CACHE_STREAM ||
+                    (p->cache_policy == LBM_CACHE_AUTO && touched_adj > kCacheResidentBytes);
     }
     // host self-check of the division constants on the extreme values
     const uint32_t probes[4] = {0u, g.nx - 1, g.nx, g.ncells - 1};
@@ -589,8 +595,8 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam
     if (!state_t || !lam_next || !lam_prev || lam_next == lam_prev)
         return fail(c, LBM_EINVAL, "state_t, lam_next, lam_prev must be set, lam_next != lam_prev");
     hipError_t e = launch_adjoint(c->g, c->p.stencil, c->p.dtype, c->p.adjoint_dtype,
-                                  c->p.equilibrium, c->p.collision == LBM_MRT, c->gen, c->coll,
-                                  state_t, lam_next, lam_prev, grad, c->sc, c->stream);
+                                  c->p.equilibrium, c->p.collision == LBM_MRT, c->gen, c->adj_nt,
+                                  c->coll, state_t, lam_next, lam_prev, grad, c->sc, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return LBM_OK;
 }

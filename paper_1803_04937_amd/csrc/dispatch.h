@@ -35,3 +35,8 @@
 #define LBM_DISPATCH_GEN(gen, BODY)                      \
     if (gen) { constexpr bool GEN = true; BODY; }        \
     else { constexpr bool GEN = false; BODY; }
+
+// Non-temporal hints on (streaming) or off (cache-resident lattices).
+#define LBM_DISPATCH_NT(BODY)                             \
+    if (nt) { constexpr bool NT = true; BODY; }           \
+    else { constexpr bool NT = false; BODY; }

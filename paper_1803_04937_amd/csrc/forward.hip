@@ -422,11 +422,6 @@ __global__ __launch_bounds__(kBlock) void k_copy(const u32x4 *__restrict__ src,
 // ---------------------------------------------------------------------------
 
 
-// Non-temporal hints on (streaming) or off (cache-resident lattices).
-#define LBM_DISPATCH_NT(BODY)                             \
-    if (nt) { constexpr bool NT = true; BODY; }           \
-    else { constexpr bool NT = false; BODY; }
-
 // Stochastic rounding exists for the 16-bit formats only.
 #define LBM_DISPATCH_SR(BODY)                                                       \
     if constexpr (DT == LBM_F16_SHIFTED || DT == LBM_BF16_SHIFTED) {                \

@@ -79,10 +79,11 @@ __host__ __device__ constexpr double wq(int qn, int q) {
 #endif
 __host__ __device__ constexpr bool hint_of(int mode, int cx) { return mode == 2 || (mode == 1 && cx == 0); }
 // The hint pays only when the data does not fit the 256 MB last-level cache:
-// the stream-collide kernels take NT = false (every access cached) for
-// lattices whose step touches at most kCacheResidentBytes, which are then
-// served from that cache between steps (10-21 % faster at 64^3-128^3).
-constexpr size_t kCacheResidentBytes = size_t(192) << 20;
+// the stream-collide and adjoint kernels take NT = false (every access
+// cached) when one step touches at most kCacheResidentBytes, which that
+// cache then serves between steps (forward +12-17 % at 96^3 FP32 and 128^3
+// FP16, adjoint +17-19 % at 96^3; streaming wins from about 310 MB up).
+constexpr size_t kCacheResidentBytes = size_t(240) << 20;
 // Occupancy (build-time tuning).  LBM_STEP_LDS_BYTES > 0 reserves that much
 // dynamic LDS per stream-collide block, which caps the resident blocks per
 // CU at floor(160 KiB / bytes) (one 256-thread block = one wave per SIMD).

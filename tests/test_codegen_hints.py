@@ -8,7 +8,8 @@ cache-policy bits of every stream-collide and adjoint instantiation:
   streaming forward (NT = 1): the 9 loads with c_x = 0 (all loads in the AA
       local step, which reads its own slots) and every store;
   cached forward (NT = 0): none;
-  adjoint: every PDF and lambda load and every lambda store.
+  streaming adjoint: every PDF and lambda load and every lambda store;
+  cached adjoint: none.
 """
 import os
 import re
@@ -58,6 +59,10 @@ def test_adjoint_hints(tmp_path):
     for name, _, nl, ns, n_loads, _ in _counts(asm):
         qn = int(re.search(r"ILi(\d+)E", name).group(1))
         gen = re.search(r"ILi\d+ELi\dELi\dELi\dELb([01])", name).group(1) == "1"
+        if name.endswith("Lb0"):          # cached policy: no hint at all
+            assert nl == 0 and ns == 0, (name, nl, ns)
+            seen += 1
+            continue
         # every PDF load and every lambda load / store is hinted (without
         # gradients the rest population's PDF is dead: 2 Q - 1 loads); kernels
         # with walls or masks also read the mask and copy lambda through

@@ -98,6 +98,11 @@ constexpr size_t kCacheResidentBytes = size_t(240) << 20;
 #ifndef LBM_STEP_LDS_BYTES
 #define LBM_STEP_LDS_BYTES 27136
 #endif
+// D3Q27 stream-collide: its 85 VGPRs allow 5 blocks per CU, which is kept;
+// 4 was +1.6 % on FP32 and -2 % on FP16, 3 lost up to 30 %.
+#ifndef LBM_STEP27_LDS_BYTES
+#define LBM_STEP27_LDS_BYTES 0
+#endif
 #ifndef LBM_ADJ_WAVES_PER_EU
 #define LBM_ADJ_WAVES_PER_EU 0
 #endif

@@ -170,6 +170,8 @@ def main():
                     help="only run the small-force driven flow in every storage type")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only run the forward throughput sweep over lattice sizes")
+    ap.add_argument("--mrt", default="",
+                    help="omega3,omega4: run the duct study with the MRT collision")
     a = ap.parse_args()
     if a.size_sweep:
         for row in size_sweep(policies=("stream", "keep")):
@@ -189,11 +191,12 @@ def main():
                 print(json.dumps(r), flush=True)
         return
     sizes = [int(v) for v in a.sizes.split(",")]
+    mrt = tuple(float(v) for v in a.mrt.split(",")) if a.mrt else None
     out = {}
     for lam2 in [float(v) for v in a.lambda2.split(",")]:
         for eq in ("standard", "improved"):
-            rows = [duct_spurious_current(D, lam2, eq, a.dtype) for D in sizes]
-            key = f"{eq}_lambda2={lam2:.4f}"
+            rows = [duct_spurious_current(D, lam2, eq, a.dtype, mrt=mrt) for D in sizes]
+            key = f"{eq}_lambda2={lam2:.4f}" + (f"_mrt={a.mrt}" if mrt else "")
             out[key] = {"rows": rows}
             if eq == "standard":
                 out[key]["order"] = convergence_order(rows)

@@ -23,12 +23,21 @@ KERNEL = re.compile(r'^(_ZN3lbm\d+(k_step_tg|k_step_aa_nb|k_step_aa_loc|k_adjoin
                     r'EEEvNS\S*:\s', re.M)
 
 
-def _assembly(src, tmp_path):
-    out = tmp_path / (src + ".s")
-    cmd = [B.HIPCC, *B.FLAGS, "--cuda-device-only", "-S", os.path.join(B.CSRC, src), "-o",
-           str(out)]
-    subprocess.run(cmd, check=True, capture_output=True)
-    return out.read_text()
+@pytest.fixture(scope="module")
+def assembly(tmp_path_factory):
+    """gfx950 assembly of both kernel files, compiled concurrently."""
+    d = tmp_path_factory.mktemp("asm")
+    procs = {}
+    for src in ("forward.hip", "adjoint.hip"):
+        cmd = [B.HIPCC, *B.FLAGS, "--cuda-device-only", "-S", os.path.join(B.CSRC, src), "-o",
+               str(d / (src + ".s"))]
+        procs[src] = subprocess.Popen(cmd, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
+    out = {}
+    for src, p in procs.items():
+        _, err = p.communicate(timeout=900)
+        assert p.returncode == 0, err.decode()[-2000:]
+        out[src] = (d / (src + ".s")).read_text()
+    return out
 
 
 def _counts(asm):
@@ -40,8 +49,8 @@ def _counts(asm):
                sum(bool(re.search(r"\bnt\b", x)) for x in stores), len(loads), len(stores))
 
 
-def test_forward_hints(tmp_path):
-    asm = _assembly("forward.hip", tmp_path)
+def test_forward_hints(assembly):
+    asm = assembly["forward.hip"]
     seen = 0
     for name, kind, nl, ns, _, _ in _counts(asm):
         qn, nt = re.search(r"ILi(\d+)E.*ELb([01])$", name).groups()
@@ -53,8 +62,8 @@ def test_forward_hints(tmp_path):
     assert seen > 500, seen
 
 
-def test_adjoint_hints(tmp_path):
-    asm = _assembly("adjoint.hip", tmp_path)
+def test_adjoint_hints(assembly):
+    asm = assembly["adjoint.hip"]
     seen = 0
     for name, _, nl, ns, n_loads, _ in _counts(asm):
         qn = int(re.search(r"ILi(\d+)E", name).group(1))

@@ -31,16 +31,19 @@
  *
  * Cells: (x, y, z), x fastest; cell index c = (z * ny + y) * nx + x.
  *
- * State buffer layout (lbm_state_bytes): structure of arrays of Q = 19 or 27
- * directions, element [q * qstride + c] of the storage type, qstride >= nx*ny*nz
- * (padded; see lbm_qstride).  What an element holds depends on the dtype:
+ * State buffer layout (lbm_state_bytes): plane-blocked arrays of Q = 19 or 27
+ * directions.  Each z-plane holds Q contiguous arrays of qstride elements
+ * (qstride = nx*ny rounded up to 64, see lbm_qstride), and the planes follow
+ * each other: element (q, x, y, z) at [(z * Q + q) * qstride + y * nx + x] of
+ * the storage type, nz * Q * qstride elements in all.  What an element holds
+ * depends on the dtype:
  *   LBM_F64, LBM_F32            f_q (post-collision)
  *   LBM_F32_SHIFTED             f_q - w_q
  *   LBM_F16_SHIFTED/BF16_SHIFTED  RNE(s (f_q - w_q)), s a per-context power
  *                               of two (lbm_scale), IEEE half / bfloat16
  * Two-grid contexts hold f*(x) at slot [q][x].  AA contexts alternate two
  * layouts; use lbm_get_pdfs for a canonical copy.  Adjoint fields use the
- * same [q * qstride + c] layout with the adjoint dtype (LBM_F64 or LBM_F32).
+ * same layout with the adjoint dtype (LBM_F64 or LBM_F32).
  *
  * Solid cells (mask value nonzero) hold the rest state f_q = w_q, are never
  * updated, and report rho = u = 0.
@@ -156,8 +159,9 @@ const char *lbm_version(void);
  * c[Q*3], w[Q], opposite[Q]. */
 void lbm_velocity_set(int32_t stencil, int32_t *c, double *w, int32_t *opposite);
 
-/* Padded q-stride (elements) and bytes of one PDF state buffer, and bytes of
- * one adjoint field, for these parameters.  Host only; no GPU needed. */
+/* qstride (elements between the direction arrays of one z-plane, see the
+ * layout above) and bytes of one PDF state buffer and of one adjoint field,
+ * for these parameters.  Host only; no GPU needed. */
 int lbm_qstride(const lbm_params *p, int64_t *qstride);
 int lbm_state_bytes(const lbm_params *p, size_t *bytes);
 int lbm_adjoint_bytes(const lbm_params *p, size_t *bytes);

@@ -39,9 +39,10 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (idx < g.ncells) {
         if (GEN && g.solid && g.solid[idx]) {
+            const int64_t pos = cell_pos(idx, g);
 #pragma unroll
             for (int q = 0; q < QN; ++q)
-                st<NT>(lam_prev + q * g.qstride + idx, ld<NT>(lam_next + q * g.qstride + idx));
+                st<NT>(lam_prev + q * g.qstride + pos, ld<NT>(lam_next + q * g.qstride + pos));
         } else {
             const Hood h = make_hood(idx, g);
             R d[QN], lam[QN];
@@ -50,18 +51,20 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
                 bool fl;
-                const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
+                int64_t pos;
+                hood_cell<GEN>(h, g, q, -1, fl, pos);
                 const typename S::T *p = state + (fl ? q : opp(q)) * g.qstride;
-                d[q] = S::template load<HL>(p, fl ? c : idx, (R)wq(QN, q), P.inv_s);
-                lam[q] = (R)ld<HL>(lam_next + q * g.qstride + idx);
+                d[q] = S::template load<HL>(p, fl ? pos : h.pos, (R)wq(QN, q), P.inv_s);
+                lam[q] = (R)ld<HL>(lam_next + q * g.qstride + h.pos);
             }
             adjoint_cell<R, EQ, QN, MRT>(d, lam, P, acc);
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
                 bool fl;
-                const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
+                int64_t pos;
+                hood_cell<GEN>(h, g, q, -1, fl, pos);
                 L *p = lam_prev + (fl ? q : opp(q)) * g.qstride;
-                st<HS>(p + (fl ? c : idx), (L)lam[q]);
+                st<HS>(p + (fl ? pos : h.pos), (L)lam[q]);
             }
         }
     }
@@ -84,6 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_objective(Geom g, int kind, double i
     const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (idx < g.ncells) {
+        const int64_t pos = cell_pos(idx, g);
         double seed[QN];
 #pragma unroll
         for (int q = 0; q < QN; ++q) seed[q] = 0.0;
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_objective(Geom g, int kind, double i
             double d[QN];
 #pragma unroll
             for (int q = 0; q < QN; ++q)
-                d[q] = (double)S::load(A + q * g.qstride, idx, (R)wq(QN, q), (R)inv_s);
+                d[q] = (double)S::load(A + q * g.qstride, pos, (R)wq(QN, q), (R)inv_s);
             double drho, jx, jy, jz;
             moments<double, QN>(d, drho, jx, jy, jz);
             const double ux = jx - ahx, uy = jy - ahy, uz = jz - ahz;
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_objective(Geom g, int kind, double i
             }
         }
 #pragma unroll
-        for (int q = 0; q < QN; ++q) lam[q * g.qstride + idx] = (L)seed[q];
+        for (int q = 0; q < QN; ++q) lam[q * g.qstride + pos] = (L)seed[q];
     }
     block_reduce<4>(acc, partials + 4 * (size_t)blockIdx.x);
 }
@@ -137,7 +141,8 @@ __global__ __launch_bounds__(kBlock) void k_init_vjp(Geom g, const double *__res
         double gO3[9][3];
         if constexpr (EQ == LBM_EQ_IMPROVED3 && NP == 9) Poly::grad_odd3<double>(ux, uy, uz, cu, gO3);
         const double g0 = Poly::rest_grad<EQ, NP>();
-        const double l0 = (double)lam0[idx];
+        const int64_t pos = cell_pos(idx, g);
+        const double l0 = (double)lam0[pos];
         gx = wq(QN, 0) * l0 * g0 * ux;
         gy = wq(QN, 0) * l0 * g0 * uy;
         gz = wq(QN, 0) * l0 * g0 * uz;
@@ -145,10 +150,10 @@ __global__ __launch_bounds__(kBlock) void k_init_vjp(Geom g, const double *__res
         for (int p = 0; p < NP; ++p) {
             const int q = 2 * p + 1;
             const double w = wq(QN, q);
-            const double ls = (double)lam0[q * g.qstride + idx] +
-                              (double)lam0[(q + 1) * g.qstride + idx];
-            const double ld = (double)lam0[q * g.qstride + idx] -
-                              (double)lam0[(q + 1) * g.qstride + idx];
+            const double ls = (double)lam0[q * g.qstride + pos] +
+                              (double)lam0[(q + 1) * g.qstride + pos];
+            const double ld = (double)lam0[q * g.qstride + pos] -
+                              (double)lam0[(q + 1) * g.qstride + pos];
             double ox = 3.0 * kC[q].x, oy = 3.0 * kC[q].y, oz = 3.0 * kC[q].z;
             if constexpr (EQ == LBM_EQ_IMPROVED3 && NP == 9) {
                 ox += gO3[p][0];

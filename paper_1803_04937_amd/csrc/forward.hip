@@ -45,18 +45,19 @@ __device__ __forceinline__ void shifted_feq(double drho, double rho0, double ux,
 // lies at x + c_q unless that cell is a wall or solid.
 template <bool GEN>
 __device__ __forceinline__ void canonical_slot(const Hood &h, const Geom &g, Layout layout,
-                                               int q, int &arr, uint32_t &cell) {
+                                               int q, int &arr, int64_t &pos) {
     if (layout == kDirect) {
         arr = q;
-        cell = h.idx;
+        pos = h.pos;
     } else if (layout == kAALocal) {
         arr = opp(q);
-        cell = h.idx;
+        pos = h.pos;
     } else {
         bool fl;
-        const uint32_t c = hood_cell<GEN>(h, g, q, +1, fl);
+        int64_t p;
+        hood_cell<GEN>(h, g, q, +1, fl, p);
         arr = fl ? q : opp(q);
-        cell = fl ? c : h.idx;
+        pos = fl ? p : h.pos;
     }
 }
 
@@ -94,10 +95,10 @@ __global__ __launch_bounds__(kBlock) void k_init(Geom g, int compressible, Layou
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
         int arr;
-        uint32_t cell;
-        canonical_slot<true>(h, g, layout, q, arr, cell);
-        S::store(A + arr * g.qstride, cell, (R)d[q], (R)wq(QN, q), (R)s);
-        if (B) S::store(B + arr * g.qstride, cell, (R)d[q], (R)wq(QN, q), (R)s);
+        int64_t pos;
+        canonical_slot<true>(h, g, layout, q, arr, pos);
+        S::store(A + arr * g.qstride, pos, (R)d[q], (R)wq(QN, q), (R)s);
+        if (B) S::store(B + arr * g.qstride, pos, (R)d[q], (R)wq(QN, q), (R)s);
     }
 }
 
@@ -146,9 +147,11 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
     static_for<QN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         bool fl;
-        const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
+        int64_t pos;
+        hood_cell<GEN>(h, g, q, -1, fl, pos);
         const typename S::T *p = src + (fl ? q : opp(q)) * g.qstride;
-        d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? c : idx, (R)wq(QN, q), P.inv_s);
+        d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
+                                                             P.inv_s);
     });
     collide<R, EQ, QN, MRT>(d, P);
     SrBits rb{SR ? mix32(idx ^ key) : 0u};
@@ -156,9 +159,9 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
         constexpr int q = decltype(qc)::value;
         constexpr bool H = fwd_store_hint<NT>(0);   // aligned stores
         if constexpr (SR)
-            store_sr<DT, H>(dst + q * g.qstride, idx, d[q], P.s, rb.next(q));
+            store_sr<DT, H>(dst + q * g.qstride, h.pos, d[q], P.s, rb.next(q));
         else
-            S::template store<H>(dst + q * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
+            S::template store<H>(dst + q * g.qstride, h.pos, d[q], (R)wq(QN, q), P.s);
     });
 }
 
@@ -184,9 +187,11 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
     static_for<QN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         bool fl;
-        const uint32_t c = hood_cell<GEN>(h, g, q, -1, fl);
+        int64_t pos;
+        hood_cell<GEN>(h, g, q, -1, fl, pos);
         const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
-        d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? c : idx, (R)wq(QN, q), P.inv_s);
+        d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
+                                                             P.inv_s);
     });
     collide<R, EQ, QN, MRT>(d, P);
     SrBits rb{SR ? mix32(idx ^ key) : 0u};
@@ -194,12 +199,13 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
         constexpr int q = decltype(qc)::value;
         constexpr bool H = fwd_store_hint<NT>(kC[q].x);
         bool fl;
-        const uint32_t c = hood_cell<GEN>(h, g, q, +1, fl);
+        int64_t pos;
+        hood_cell<GEN>(h, g, q, +1, fl, pos);
         typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
         if constexpr (SR)
-            store_sr<DT, H>(p, fl ? c : idx, d[q], P.s, rb.next(q));
+            store_sr<DT, H>(p, fl ? pos : h.pos, d[q], P.s, rb.next(q));
         else
-            S::template store<H>(p, fl ? c : idx, d[q], (R)wq(QN, q), P.s);
+            S::template store<H>(p, fl ? pos : h.pos, d[q], (R)wq(QN, q), P.s);
     });
 }
 
@@ -211,10 +217,11 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename St
     const uint32_t idx = cell_index();
     if (idx >= g.ncells) return;
     if (GEN && is_solid(g, idx)) return;
+    const int64_t pos = cell_pos(idx, g);
     R d[QN];
     static_for<QN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        d[q] = S::template load<fwd_load_hint<NT>(0)>(A + q * g.qstride, idx, (R)wq(QN, q),
+        d[q] = S::template load<fwd_load_hint<NT>(0)>(A + q * g.qstride, pos, (R)wq(QN, q),
                                                       P.inv_s);
     });
     collide<R, EQ, QN, MRT>(d, P);
@@ -223,9 +230,9 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename St
         constexpr int q = decltype(qc)::value;
         constexpr bool H = fwd_store_hint<NT>(0);
         if constexpr (SR)
-            store_sr<DT, H>(A + opp(q) * g.qstride, idx, d[q], P.s, rb.next(q));
+            store_sr<DT, H>(A + opp(q) * g.qstride, pos, d[q], P.s, rb.next(q));
         else
-            S::template store<H>(A + opp(q) * g.qstride, idx, d[q], (R)wq(QN, q), P.s);
+            S::template store<H>(A + opp(q) * g.qstride, pos, d[q], (R)wq(QN, q), P.s);
     });
 }
 
@@ -247,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_get(Geom g, Layout layout, double in
         double v = wq(QN, q);
         if (!solid) {
             int arr;
-            uint32_t cell;
+            int64_t cell;
             canonical_slot<true>(h, g, layout, q, arr, cell);
             v = load_canonical<DT>(A + arr * g.qstride, cell, wq(QN, q), inv_s);
         }
@@ -278,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(Geom g, Layout layout, double
         double v = wq(QN, q);
         if (!solid) {
             int arr;
-            uint32_t cell;
+            int64_t cell;
             canonical_slot<true>(h, g, layout, q, arr, cell);
             v = load_canonical<DT>(A + arr * g.qstride, cell, wq(QN, q), inv_s);
         }
@@ -299,10 +306,10 @@ __global__ __launch_bounds__(kBlock) void k_set(Geom g, Layout layout, double s,
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
         if (solid) {
-            S::store(A + q * g.qstride, idx, (R)0, (R)wq(QN, q), (R)s);
+            S::store(A + q * g.qstride, h.pos, (R)0, (R)wq(QN, q), (R)s);
         } else {
             int arr;
-            uint32_t cell;
+            int64_t cell;
             canonical_slot<true>(h, g, layout, q, arr, cell);
             store_canonical<DT>(A + arr * g.qstride, cell, in[(size_t)q * g.ncells + idx],
                                 wq(QN, q), s);
@@ -331,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Geom g, Layout layout, doubl
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
                 int arr;
-                uint32_t cell;
+                int64_t cell;
                 canonical_slot<true>(h, g, layout, q, arr, cell);
                 d[q] = (double)S::load(A + arr * g.qstride, cell, (R)wq(QN, q), (R)inv_s);
             }

@@ -161,17 +161,17 @@ struct Store<LBM_F64> {
     using T = double;
     using R = double;
     template <bool NT = true>
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) {
+    static __device__ __forceinline__ R load(const T *p, int64_t i, R w, R) {
         return ld<NT>(p + i) - w;
     }
     template <bool NT = true>
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) {
+    static __device__ __forceinline__ void store(T *p, int64_t i, R d, R w, R) {
         st<NT>(p + i, (T)(d + w));
     }
-    static __device__ __forceinline__ double load_f(const T *p, uint32_t i, double, double) {
+    static __device__ __forceinline__ double load_f(const T *p, int64_t i, double, double) {
         return ld<true>(p + i);
     }
-    static __device__ __forceinline__ void store_f(T *p, uint32_t i, double f, double, double) {
+    static __device__ __forceinline__ void store_f(T *p, int64_t i, double f, double, double) {
         st<true>(p + i, f);
     }
 };
@@ -180,17 +180,17 @@ struct Store<LBM_F32> {
     using T = float;
     using R = float;
     template <bool NT = true>
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R w, R) {
+    static __device__ __forceinline__ R load(const T *p, int64_t i, R w, R) {
         return ld<NT>(p + i) - w;
     }
     template <bool NT = true>
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R w, R) {
+    static __device__ __forceinline__ void store(T *p, int64_t i, R d, R w, R) {
         st<NT>(p + i, (T)(d + w));
     }
-    static __device__ __forceinline__ double load_f(const T *p, uint32_t i, double, double) {
+    static __device__ __forceinline__ double load_f(const T *p, int64_t i, double, double) {
         return ld<true>(p + i);
     }
-    static __device__ __forceinline__ void store_f(T *p, uint32_t i, double f, double, double) {
+    static __device__ __forceinline__ void store_f(T *p, int64_t i, double f, double, double) {
         st<true>(p + i, (float)f);
     }
 };
@@ -199,11 +199,11 @@ struct Store<LBM_F32_SHIFTED> {
     using T = float;
     using R = float;
     template <bool NT = true>
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R) {
+    static __device__ __forceinline__ R load(const T *p, int64_t i, R, R) {
         return ld<NT>(p + i);
     }
     template <bool NT = true>
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R) {
+    static __device__ __forceinline__ void store(T *p, int64_t i, R d, R, R) {
         st<NT>(p + i, d);
     }
 };
@@ -212,11 +212,11 @@ struct Store<LBM_F16_SHIFTED> {
     using T = _Float16;
     using R = float;
     template <bool NT = true>
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s) {
+    static __device__ __forceinline__ R load(const T *p, int64_t i, R, R inv_s) {
         return static_cast<float>(ld<NT>(p + i)) * inv_s;
     }
     template <bool NT = true>
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s) {
+    static __device__ __forceinline__ void store(T *p, int64_t i, R d, R, R s) {
         st<NT>(p + i, static_cast<_Float16>(d * s));  // round to nearest even
     }
 };
@@ -225,11 +225,11 @@ struct Store<LBM_BF16_SHIFTED> {
     using T = __bf16;
     using R = float;
     template <bool NT = true>
-    static __device__ __forceinline__ R load(const T *p, uint32_t i, R, R inv_s) {
+    static __device__ __forceinline__ R load(const T *p, int64_t i, R, R inv_s) {
         return static_cast<float>(ld<NT>(p + i)) * inv_s;
     }
     template <bool NT = true>
-    static __device__ __forceinline__ void store(T *p, uint32_t i, R d, R, R s) {
+    static __device__ __forceinline__ void store(T *p, int64_t i, R d, R, R s) {
         st<NT>(p + i, static_cast<__bf16>(d * s));  // round to nearest even
     }
 };
@@ -298,7 +298,7 @@ __device__ __forceinline__ float sr_truncate(float v, uint32_t r) {
 }
 
 template <int DT, bool NT = true>
-__device__ __forceinline__ void store_sr(typename Store<DT>::T *p, uint32_t i, float d, float s,
+__device__ __forceinline__ void store_sr(typename Store<DT>::T *p, int64_t i, float d, float s,
                                          uint32_t r) {
     if constexpr (DT == LBM_F16_SHIFTED)
         st<NT>(p + i, static_cast<_Float16>(sr_truncate<13>(d * s, r)));
@@ -309,7 +309,7 @@ __device__ __forceinline__ void store_sr(typename Store<DT>::T *p, uint32_t i, f
 // Canonical (FP64) access: f = w + d.  The raw formats override these with
 // exact copies.
 template <int DT>
-__device__ __forceinline__ double load_canonical(const typename Store<DT>::T *p, uint32_t i,
+__device__ __forceinline__ double load_canonical(const typename Store<DT>::T *p, int64_t i,
                                                  double w, double inv_s) {
     if constexpr (DT == LBM_F64 || DT == LBM_F32) {
         return Store<DT>::load_f(p, i, w, inv_s);
@@ -319,7 +319,7 @@ __device__ __forceinline__ double load_canonical(const typename Store<DT>::T *p,
     }
 }
 template <int DT>
-__device__ __forceinline__ void store_canonical(typename Store<DT>::T *p, uint32_t i, double f,
+__device__ __forceinline__ void store_canonical(typename Store<DT>::T *p, int64_t i, double f,
                                                 double w, double s) {
     if constexpr (DT == LBM_F64 || DT == LBM_F32) {
         Store<DT>::store_f(p, i, f, w, s);
@@ -357,20 +357,31 @@ __host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
 // ---------------------------------------------------------------------------
 // Geometry shared by all cell kernels.
 // ---------------------------------------------------------------------------
+// PDF and adjoint buffers are plane-blocked: the Q direction arrays of each
+// z-plane are contiguous, element (q, cell) at (z Q + q) qstride + y nx + x,
+// i.e. q qstride + pos(cell) with pos(cell) = cell + z zskip.
 struct Geom {
     uint32_t ncells, nx, ny, nz, nxy;
-    FastDiv div_nx, div_ny;
+    FastDiv div_nx, div_ny, div_nxy;
     int32_t per[3];       // periodic flags
-    int64_t qstride;      // elements between consecutive q arrays
+    int64_t qstride;      // elements between consecutive q arrays of one plane
+    int64_t zskip;        // Q qstride - nxy
     const uint8_t *solid; // nullptr: all fluid
 };
+
+// Buffer position of cell idx (add q * qstride for direction q).
+__device__ __forceinline__ int64_t cell_pos(uint32_t idx, const Geom &g) {
+    return (int64_t)idx + (int64_t)fdiv(idx, g.div_nxy) * g.zskip;
+}
 
 // Per-thread neighbourhood of one cell: index offsets of x + dx, y + dy,
 // z + dz for dx, dy, dz in {-1, 0, +1} (periodic wrap applied) and whether
 // each exists (false beyond a wall).
 struct Hood {
     uint32_t idx;
+    int64_t pos;          // buffer position of the cell
     int32_t ox[3], oy[3], oz[3];
+    int64_t pz[3];        // plane term z' zskip of the planes z - 1, z, z + 1
     bool vx[3], vy[3], vz[3];
 };
 
@@ -399,17 +410,23 @@ __device__ __forceinline__ Hood make_hood(uint32_t idx, const Geom &g) {
     h.oz[2] = z == g.nz - 1 ? -(nz - 1) * nxy : nxy;
     h.vz[0] = z != 0 || g.per[2];
     h.vz[2] = z != g.nz - 1 || g.per[2];
+    h.pz[0] = (int64_t)(z == 0 ? g.nz - 1 : z - 1) * g.zskip;
+    h.pz[1] = (int64_t)z * g.zskip;
+    h.pz[2] = (int64_t)(z == g.nz - 1 ? 0 : z + 1) * g.zskip;
+    h.pos = (int64_t)idx + h.pz[1];
     return h;
 }
 
-// Cell x + s c_q (s = -1: pull source, s = +1: push target) and whether it
-// is fluid (false for walls and solid cells).  GEN = false assumes a fully
-// periodic domain without solid cells.
+// Cell x + s c_q (s = -1: pull source, s = +1: push target), its buffer
+// position, and whether it is fluid (false for walls and solid cells; the
+// position is then meaningless).  GEN = false assumes a fully periodic
+// domain without solid cells.
 template <bool GEN>
 __device__ __forceinline__ uint32_t hood_cell(const Hood &h, const Geom &g, int q, int s,
-                                              bool &fluid) {
+                                              bool &fluid, int64_t &pos) {
     const int dx = s * kC[q].x + 1, dy = s * kC[q].y + 1, dz = s * kC[q].z + 1;
     uint32_t c = (uint32_t)((int32_t)h.idx + h.ox[dx] + h.oy[dy] + h.oz[dz]);
+    pos = (int64_t)c + h.pz[dz];
     if (!GEN) {
         fluid = true;
         return c;

@@ -86,17 +86,23 @@ class Lattice:
 
     # -- buffers -------------------------------------------------------------
     def new_state(self) -> torch.Tensor:
-        """A state buffer of this lattice's layout: tensor (Q, qstride)."""
-        return torch.empty((self.q, self.qstride), dtype=self.storage_dtype, device=self.device)
+        """A state buffer of this lattice's layout: tensor (nz, Q, qstride),
+        the Q direction arrays of each z-plane contiguous."""
+        return torch.empty((self.shape[0], self.q, self.qstride), dtype=self.storage_dtype,
+                           device=self.device)
 
     def new_adjoint(self, zero: bool = True) -> torch.Tensor:
-        """An adjoint field: tensor (Q, qstride) of the adjoint dtype."""
+        """An adjoint field: tensor (nz, Q, qstride) of the adjoint dtype."""
         f = torch.zeros if zero else torch.empty
-        return f((self.q, self.qstride), dtype=self.adjoint_dtype, device=self.device)
+        return f((self.shape[0], self.q, self.qstride), dtype=self.adjoint_dtype,
+                 device=self.device)
 
     def state_view(self, buf: torch.Tensor) -> torch.Tensor:
-        """(Q, nz, ny, nx) view of the cells of a state or adjoint buffer."""
-        return buf[:, :self.ncells].view((buf.shape[0],) + self.shape)
+        """(Q, nz, ny, nx) view (not a copy) of the cells of a state or adjoint
+        buffer."""
+        nz, ny, nx = self.shape
+        planes = buf.view(nz, self.q, self.qstride)[:, :, :ny * nx]
+        return planes.unflatten(2, (ny, nx)).permute(1, 0, 2, 3)
 
     @property
     def ctx(self):

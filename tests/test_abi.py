@@ -48,18 +48,22 @@ def test_version(capi):
 
 
 def test_layout_sizes(capi):
+    """Plane-blocked buffers: nz planes of Q arrays of qstride elements,
+    qstride = nx*ny rounded up to 64."""
     p = capi.make_params(256, 256, 256, dtype=capi.LBM_F32)
     qs = capi.lbm_qstride(p)
-    assert qs >= 256 ** 3 and qs % 64 == 0
-    assert capi.lbm_state_bytes(p) == 19 * qs * 4
-    assert capi.lbm_adjoint_bytes(p) == 19 * qs * 4
+    assert qs == 256 * 256
+    assert capi.lbm_state_bytes(p) == 256 * 19 * qs * 4
+    assert capi.lbm_adjoint_bytes(p) == 256 * 19 * qs * 4
     p16 = capi.make_params(512, 512, 512, dtype=capi.LBM_F16_SHIFTED)
-    assert capi.lbm_state_bytes(p16) == 19 * capi.lbm_qstride(p16) * 2
+    assert capi.lbm_state_bytes(p16) == 512 * 19 * capi.lbm_qstride(p16) * 2
     p64 = capi.make_params(7, 5, 3, dtype=capi.LBM_F64)
-    assert capi.lbm_state_bytes(p64) == 19 * capi.lbm_qstride(p64) * 8
-    p27 = capi.make_params(64, 64, 64, dtype=capi.LBM_F32, stencil=27)
-    assert capi.lbm_state_bytes(p27) == 27 * capi.lbm_qstride(p27) * 4
-    assert capi.lbm_adjoint_bytes(p27) == 27 * capi.lbm_qstride(p27) * 4
+    assert capi.lbm_qstride(p64) == 64
+    assert capi.lbm_state_bytes(p64) == 3 * 19 * 64 * 8
+    p27 = capi.make_params(37, 19, 15, dtype=capi.LBM_F32, stencil=27)
+    assert capi.lbm_qstride(p27) == 704 and 704 % 64 == 0 and 704 >= 37 * 19
+    assert capi.lbm_state_bytes(p27) == 15 * 27 * 704 * 4
+    assert capi.lbm_adjoint_bytes(p27) == 15 * 27 * 704 * 4
 
 
 BAD = [

@@ -48,7 +48,7 @@ def test_wide_adjoint_step_matches_oracle(name, dtype):
     lat.set_pdfs(dev(f))
     f_stored = host(lat.get_pdfs())       # the state as stored (rounded below FP64)
     ln, lp = lat.new_adjoint(), lat.new_adjoint()
-    assert ln.shape[0] == cfg.q
+    assert lat.state_view(ln).shape[0] == cfg.q
     _load(lat, ln, lam)
     grad = torch.zeros(4, dtype=torch.float64, device="cuda")
     lat.adjoint_step(lat.state, ln, lp, grad)

@@ -88,7 +88,7 @@ def test_d3q27_adjoint_field_and_compressible_refusal():
     cfg, kw = case(8, 8, 8, stencil=27)
     lat = lattice(cfg, kw, np.zeros((3,) + cfg.shape), dtype="f32")
     lam = lat.new_adjoint()
-    assert lam.shape == (27, lat.qstride)
+    assert lat.state_view(lam).shape == (27,) + cfg.shape
     lat.close()
     cfg, kw = case(8, 8, 8, stencil=27, compressible=True)
     lat = lattice(cfg, kw, np.zeros((3,) + cfg.shape), dtype="f32")

@@ -27,6 +27,20 @@ struct Lam<LBM_F32> {
 // lam_t[rbar][x] when x - c_r is a wall or solid).  Each f_t slot is read by
 // exactly one cell in the forward step, so each lam_t slot is written
 // exactly once.  Solid cells copy lam through.
+//
+// Pushes along x would leave every wave's store one element off the
+// 256-byte segments of the array, so two waves write parts of the same
+// memory sectors.  Those pushes go through LDS instead: the value for slot
+// (x - c_r, y - c_ry, z - c_rz) is parked at the block-local index of
+// cell (x - c_r, y, z) (the x shift wraps within the row), and after one
+// barrier the thread of that cell stores it at its own x, so each store is
+// as aligned as the forward's.  A thread reads its parked slot exactly when
+// its writer cell (x + c_r, wrapped) lies in the block, is fluid, and
+// pulls from a fluid cell: the writer has then filled the slot.  A push
+// that cannot be parked (target cell in another block, or bounce-back)
+// goes to the writer's own outbox slot and is stored after the barrier.
+// The writer loop thus holds no global stores for these directions, which
+// keeps its register footprint below that of storing every push directly.
 template <int QN, int DT, int LT, int EQ, bool GEN, bool MRT, bool GRAD, bool NT>
 __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     Geom g, Coll<typename Store<DT>::R> P, const typename Store<DT>::T *__restrict__ state,
@@ -35,36 +49,78 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     using S = Store<DT>;
     using R = typename S::R;
     using L = typename Lam<LT>::T;
-    const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+    constexpr const XTab &X = QN == 19 ? kXTab19 : kXTab27;
+    // [k][0, kBlock): parked by target cell; [k][kBlock, 2 kBlock): outbox
+    __shared__ L xbuf[X.n][2 * kBlock];
+    const int j = threadIdx.x;
+    const uint32_t idx = blockIdx.x * kBlock + j;
+    const bool valid = idx < g.ncells;
+    const bool fluid = valid && !(GEN && g.solid && g.solid[idx]);
+    // one hint for every direction: plain unrolled loops suffice
+    constexpr bool HL = NT && LBM_NT_ADJ_LOADS != 0, HS = NT && LBM_NT_ADJ_STORES != 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (idx < g.ncells) {
-        if (GEN && g.solid && g.solid[idx]) {
-            const int64_t pos = cell_pos(idx, g);
+    if (fluid) {
+        const Hood h = make_hood(idx, g);
+        R d[QN], lam[QN];
 #pragma unroll
-            for (int q = 0; q < QN; ++q)
-                st<NT>(lam_prev + q * g.qstride + pos, ld<NT>(lam_next + q * g.qstride + pos));
-        } else {
-            const Hood h = make_hood(idx, g);
-            R d[QN], lam[QN];
-            // one hint for every direction: plain unrolled loops suffice
-            constexpr bool HL = NT && LBM_NT_ADJ_LOADS != 0, HS = NT && LBM_NT_ADJ_STORES != 0;
+        for (int q = 0; q < QN; ++q) {
+            bool fl;
+            int64_t pos;
+            hood_cell<GEN>(h, g, q, -1, fl, pos);
+            const typename S::T *p = state + (fl ? q : opp(q)) * g.qstride;
+            d[q] = S::template load<HL>(p, fl ? pos : h.pos, (R)wq(QN, q), P.inv_s);
+            lam[q] = (R)ld<HL>(lam_next + q * g.qstride + h.pos);
+        }
+        adjoint_cell<R, EQ, QN, MRT>(d, lam, P, acc);
 #pragma unroll
-            for (int q = 0; q < QN; ++q) {
-                bool fl;
-                int64_t pos;
-                hood_cell<GEN>(h, g, q, -1, fl, pos);
-                const typename S::T *p = state + (fl ? q : opp(q)) * g.qstride;
-                d[q] = S::template load<HL>(p, fl ? pos : h.pos, (R)wq(QN, q), P.inv_s);
-                lam[q] = (R)ld<HL>(lam_next + q * g.qstride + h.pos);
-            }
-            adjoint_cell<R, EQ, QN, MRT>(d, lam, P, acc);
-#pragma unroll
-            for (int q = 0; q < QN; ++q) {
-                bool fl;
-                int64_t pos;
-                hood_cell<GEN>(h, g, q, -1, fl, pos);
+        for (int q = 0; q < QN; ++q) {
+            bool fl;
+            int64_t pos;
+            hood_cell<GEN>(h, g, q, -1, fl, pos);
+            if (kC[q].x != 0) {
+                const int jr = j + h.ox[1 - kC[q].x];
+                const bool park = fl && jr >= 0 && jr < kBlock;
+                xbuf[X.rank[q]][park ? jr : kBlock + j] = (L)lam[q];
+            } else {
                 L *p = lam_prev + (fl ? q : opp(q)) * g.qstride;
                 st<HS>(p + (fl ? pos : h.pos), (L)lam[q]);
+            }
+        }
+    } else if (valid) {
+        const int64_t pos = cell_pos(idx, g);
+#pragma unroll
+        for (int q = 0; q < QN; ++q)
+            st<NT>(lam_prev + q * g.qstride + pos, ld<NT>(lam_next + q * g.qstride + pos));
+    }
+    __syncthreads();
+    if (valid) {
+        // Rebuild the neighbourhood from an opaque copy of idx, so that the
+        // compiler recomputes these few integer terms here instead of
+        // keeping the pull positions live through the collision.
+        uint32_t idx2 = idx;
+        asm volatile("" : "+v"(idx2));
+        const Hood h = make_hood(idx2, g);
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            if (kC[q].x == 0) continue;
+            bool fl;
+            int64_t pos;
+            // parked slot: the push of writer x + c_x into this cell's x
+            const int dw = h.ox[1 + kC[q].x];
+            const int jw = j + dw;
+            if (jw >= 0 && jw < kBlock) {
+                hood_cell<GEN>(h, g, X.q0[q], -1, fl, pos);
+                if (!GEN || (h.vx[1 + kC[q].x] && fl && !(g.solid && g.solid[idx2 + dw])))
+                    st<HS>(lam_prev + q * g.qstride + pos, xbuf[X.rank[q]][j]);
+            }
+            // outbox: this cell's own push that was not parked
+            if (fluid) {
+                hood_cell<GEN>(h, g, q, -1, fl, pos);
+                const int jr = j + h.ox[1 - kC[q].x];
+                if (!(fl && jr >= 0 && jr < kBlock)) {
+                    L *p = lam_prev + (fl ? q : opp(q)) * g.qstride;
+                    st<HS>(p + (fl ? pos : h.pos), xbuf[X.rank[q]][kBlock + j]);
+                }
             }
         }
     }

@@ -47,6 +47,26 @@ __host__ __device__ constexpr double wq(int qn, int q) {
                               : (q <= 6 ? 2.0 / 27.0 : (q <= 18 ? 1.0 / 54.0 : 1.0 / 216.0)));
 }
 
+// Directions that shift along x, for kernels that write them x-shifted:
+// rank[q] numbers the directions with c_x != 0 (-1 for the others), and
+// q0[q] is the direction (0, c_y, c_z) that keeps q's row shift.
+struct XTab {
+    int n;
+    int rank[kQMax];
+    int q0[kQMax];
+};
+constexpr XTab make_xtab(int qn) {
+    XTab t{};
+    for (int q = 0; q < qn; ++q) {
+        t.rank[q] = kC[q].x != 0 ? t.n++ : -1;
+        for (int p = 0; p < qn; ++p)
+            if (kC[p].x == 0 && kC[p].y == kC[q].y && kC[p].z == kC[q].z) t.q0[q] = p;
+    }
+    return t;
+}
+constexpr XTab kXTab19 = make_xtab(19), kXTab27 = make_xtab(27);
+static_assert(kXTab19.n == 10 && kXTab27.n == 18, "x-shifted direction count");
+
 // ---------------------------------------------------------------------------
 // Streaming memory access.  Every PDF and adjoint value is read once and
 // written once per step, so accesses may carry the non-temporal hint (NT).

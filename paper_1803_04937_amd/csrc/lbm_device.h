@@ -107,16 +107,24 @@ constexpr size_t kCacheResidentBytes = size_t(240) << 20;
 // Occupancy (build-time tuning).  LBM_STEP_LDS_BYTES > 0 reserves that much
 // dynamic LDS per stream-collide block, which caps the resident blocks per
 // CU at floor(160 KiB / bytes) (one 256-thread block = one wave per SIMD).
-// The default, 26.5 KiB, allows 6 blocks per CU: measured on MI355X at 256^3,
-// the two-grid pull moves 3 % more bytes per second with 4 to 6 resident
-// blocks than with the 8 its registers allow (FP32 5.57 -> 5.75 TB/s), and
-// falls off at 3; the AA steps do not change.
+// Measured on MI355X at 256^3 in the plane-blocked layout, two-grid pull:
+//   blocks per CU       8      6      5      4
+//   FP32 (TB/s)       6.07   6.25   6.33   6.32
+//   shifted FP32      6.29   6.36   6.42   6.42
+//   FP16 shifted      6.04   6.21   5.88   5.86
+//   BF16 shifted      6.06   6.25   5.98   5.97
+//   FP64              6.09   6.09   6.09   6.09  (registers allow 4)
+// so 4-byte storage takes 5 blocks (32 KiB) and the others 6 (26.5 KiB);
+// the AA steps do not change.
 // LBM_ADJ_WAVES_PER_EU > 0 asks the compiler to fit the adjoint kernel into
 // that many waves per SIMD, LBM_ADJ_LDS_BYTES caps its resident blocks like
-// LBM_STEP_LDS_BYTES.  Its registers allow 3 blocks per CU; 4 (fitted by the
-// compiler) was 3.5 % slower and 2 was 6 % slower, so neither is set.
+// LBM_STEP_LDS_BYTES.  The FP32 adjoint's registers allow 4 blocks per CU,
+// which is best (3: 7 % slower, 2: 32 % slower), so neither is set.
 #ifndef LBM_STEP_LDS_BYTES
 #define LBM_STEP_LDS_BYTES 27136
+#endif
+#ifndef LBM_STEP_LDS_BYTES_4B
+#define LBM_STEP_LDS_BYTES_4B 32768
 #endif
 // D3Q27 stream-collide: its 85 VGPRs allow 5 blocks per CU, which is kept;
 // 4 was +1.6 % on FP32 and -2 % on FP16, 3 lost up to 30 %.

@@ -139,30 +139,56 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
                                                     uint32_t key) {
     using S = Store<DT>;
     using R = typename S::R;
-    const uint32_t idx = cell_index();
-    if (idx >= g.ncells) return;
-    if (GEN && is_solid(g, idx)) return;
-    const Hood h = make_hood(idx, g);
+    using T = typename S::T;
     R d[QN];
-    static_for<QN>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        bool fl;
-        int64_t pos;
-        hood_cell<GEN>(h, g, q, -1, fl, pos);
-        const typename S::T *p = src + (fl ? q : opp(q)) * g.qstride;
-        d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
-                                                             P.inv_s);
-    });
-    collide<R, EQ, QN, MRT>(d, P);
-    SrBits rb{SR ? mix32(idx ^ key) : 0u};
-    static_for<QN>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr bool H = fwd_store_hint<NT>(0);   // aligned stores
-        if constexpr (SR)
-            store_sr<DT, H>(dst + q * g.qstride, h.pos, d[q], P.s, rb.next(q));
-        else
-            S::template store<H>(dst + q * g.qstride, h.pos, d[q], (R)wq(QN, q), P.s);
-    });
+    if constexpr (!GEN) {
+        // periodic, no mask: planar launch (blockIdx.y = z)
+        const uint32_t z = blockIdx.y, p = blockIdx.x * kBlock + threadIdx.x;
+        if (p >= g.nxy) return;
+        const PlaneHood h = make_plane_hood(p, z, g);
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const T *base = src + ((int64_t)h.zp[1 - kC[q].z] * QN + q) * g.qstride;
+            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(
+                at_bytes(base, plane_off<T>(h, q, -1)), 0, (R)wq(QN, q), P.inv_s);
+        });
+        collide<R, EQ, QN, MRT>(d, P);
+        SrBits rb{SR ? mix32((z * g.nxy + p) ^ key) : 0u};
+        const uint32_t off = p * (uint32_t)sizeof(T);
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr bool H = fwd_store_hint<NT>(0);   // aligned stores
+            T *o = at_bytes(dst + ((int64_t)z * QN + q) * g.qstride, off);
+            if constexpr (SR)
+                store_sr<DT, H>(o, 0, d[q], P.s, rb.next(q));
+            else
+                S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
+        });
+    } else {
+        const uint32_t idx = cell_index();
+        if (idx >= g.ncells) return;
+        if (is_solid(g, idx)) return;
+        const Hood h = make_hood(idx, g);
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            bool fl;
+            int64_t pos;
+            hood_cell<GEN>(h, g, q, -1, fl, pos);
+            const T *p = src + (fl ? q : opp(q)) * g.qstride;
+            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
+                                                                 P.inv_s);
+        });
+        collide<R, EQ, QN, MRT>(d, P);
+        SrBits rb{SR ? mix32(idx ^ key) : 0u};
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr bool H = fwd_store_hint<NT>(0);   // aligned stores
+            if constexpr (SR)
+                store_sr<DT, H>(dst + q * g.qstride, h.pos, d[q], P.s, rb.next(q));
+            else
+                S::template store<H>(dst + q * g.qstride, h.pos, d[q], (R)wq(QN, q), P.s);
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -179,11 +205,37 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
                                                        typename Store<DT>::T *A, uint32_t key) {
     using S = Store<DT>;
     using R = typename S::R;
+    using T = typename S::T;
+    R d[QN];
+    if constexpr (!GEN) {
+        // periodic, no mask: planar launch (blockIdx.y = z)
+        const uint32_t z = blockIdx.y, p = blockIdx.x * kBlock + threadIdx.x;
+        if (p >= g.nxy) return;
+        const PlaneHood h = make_plane_hood(p, z, g);
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const T *base = A + ((int64_t)h.zp[1 - kC[q].z] * QN + opp(q)) * g.qstride;
+            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(
+                at_bytes(base, plane_off<T>(h, q, -1)), 0, (R)wq(QN, q), P.inv_s);
+        });
+        collide<R, EQ, QN, MRT>(d, P);
+        SrBits rb{SR ? mix32((z * g.nxy + p) ^ key) : 0u};
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr bool H = fwd_store_hint<NT>(kC[q].x);
+            T *o = at_bytes(A + ((int64_t)h.zp[1 + kC[q].z] * QN + q) * g.qstride,
+                            plane_off<T>(h, q, +1));
+            if constexpr (SR)
+                store_sr<DT, H>(o, 0, d[q], P.s, rb.next(q));
+            else
+                S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
+        });
+        return;
+    }
     const uint32_t idx = cell_index();
     if (idx >= g.ncells) return;
-    if (GEN && is_solid(g, idx)) return;
+    if (is_solid(g, idx)) return;
     const Hood h = make_hood(idx, g);
-    R d[QN];
     static_for<QN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         bool fl;
@@ -214,11 +266,36 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename St
                                                         typename Store<DT>::T *A, uint32_t key) {
     using S = Store<DT>;
     using R = typename S::R;
+    using T = typename S::T;
+    R d[QN];
+    if constexpr (!GEN) {
+        // periodic, no mask: planar launch (blockIdx.y = z)
+        const uint32_t z = blockIdx.y, p = blockIdx.x * kBlock + threadIdx.x;
+        if (p >= g.nxy) return;
+        const uint32_t off = p * (uint32_t)sizeof(T);
+        T *plane = A + (int64_t)z * QN * g.qstride;
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            d[q] = S::template load<fwd_load_hint<NT>(0)>(at_bytes(plane + q * g.qstride, off), 0,
+                                                          (R)wq(QN, q), P.inv_s);
+        });
+        collide<R, EQ, QN, MRT>(d, P);
+        SrBits rb{SR ? mix32((z * g.nxy + p) ^ key) : 0u};
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr bool H = fwd_store_hint<NT>(0);
+            T *o = at_bytes(plane + opp(q) * g.qstride, off);
+            if constexpr (SR)
+                store_sr<DT, H>(o, 0, d[q], P.s, rb.next(q));
+            else
+                S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
+        });
+        return;
+    }
     const uint32_t idx = cell_index();
     if (idx >= g.ncells) return;
-    if (GEN && is_solid(g, idx)) return;
+    if (is_solid(g, idx)) return;
     const int64_t pos = cell_pos(idx, g);
-    R d[QN];
     static_for<QN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         d[q] = S::template load<fwd_load_hint<NT>(0)>(A + q * g.qstride, pos, (R)wq(QN, q),
@@ -470,7 +547,10 @@ hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, c
 hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
                           bool sr, bool nt, uint32_t key, const CollBoth &P, const void *src,
                           void *dst, hipStream_t st) {
-    const dim3 grid(cell_blocks(g)), block(kBlock);
+    // GEN = false runs the planar launch; lattices it cannot address take the
+    // general kernel, which is exact for periodic lattices without a mask too.
+    gen = gen || !planar_ok(g);
+    const dim3 grid = gen ? dim3(cell_blocks(g)) : plane_grid(g), block(kBlock);
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(
         LBM_DISPATCH_SR(LBM_DISPATCH_NT({
         using T = typename Store<DT>::T;
@@ -483,7 +563,8 @@ hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bo
 hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
                           bool sr, bool nt, uint32_t key, bool neighbor, const CollBoth &P,
                           void *A, hipStream_t st) {
-    const dim3 grid(cell_blocks(g)), block(kBlock);
+    gen = gen || !planar_ok(g);   // as in launch_step_tg
+    const dim3 grid = gen ? dim3(cell_blocks(g)) : plane_grid(g), block(kBlock);
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(
         LBM_DISPATCH_SR(LBM_DISPATCH_NT({
         using T = typename Store<DT>::T;

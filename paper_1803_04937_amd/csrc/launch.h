@@ -86,5 +86,11 @@ hipError_t launch_finalize(const Scratch &sc, uint32_t nblocks, int nvals, int o
 hipError_t launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t st);
 
 inline uint32_t cell_blocks(const Geom &g) { return (g.ncells + kBlock - 1) / kBlock; }
+// Planar launch (blocks of one z-plane each): possible when the planes fit
+// the grid's second dimension and a plane's FP64 bytes fit 32-bit offsets.
+inline bool planar_ok(const Geom &g) {
+    return g.nz <= kMaxPlanes && (uint64_t)g.nxy * sizeof(double) <= 0xffffffffull;
+}
+inline dim3 plane_grid(const Geom &g) { return dim3((g.nxy + kBlock - 1) / kBlock, g.nz); }
 
 }  // namespace lbm

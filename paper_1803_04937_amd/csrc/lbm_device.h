@@ -126,10 +126,11 @@ constexpr size_t kCacheResidentBytes = size_t(240) << 20;
 #ifndef LBM_STEP_LDS_BYTES_4B
 #define LBM_STEP_LDS_BYTES_4B 32768
 #endif
-// D3Q27 stream-collide: its 85 VGPRs allow 5 blocks per CU, which is kept;
-// 4 was +1.6 % on FP32 and -2 % on FP16, 3 lost up to 30 %.
+// D3Q27 stream-collide: its 84 VGPRs allow 5 blocks per CU.  With the
+// planar launch 4 is best (FP32 1.5 % and FP16 1 % faster than 5, measured
+// side by side); 3 lost up to 30 % before.
 #ifndef LBM_STEP27_LDS_BYTES
-#define LBM_STEP27_LDS_BYTES 0
+#define LBM_STEP27_LDS_BYTES 40960
 #endif
 #ifndef LBM_ADJ_WAVES_PER_EU
 #define LBM_ADJ_WAVES_PER_EU 0
@@ -400,6 +401,49 @@ struct Geom {
 // Buffer position of cell idx (add q * qstride for direction q).
 __device__ __forceinline__ int64_t cell_pos(uint32_t idx, const Geom &g) {
     return (int64_t)idx + (int64_t)fdiv(idx, g.div_nxy) * g.zskip;
+}
+
+// Planar launch of a periodic lattice without a mask: blockIdx.y is z and
+// blockIdx.x runs over 256-cell segments of the plane, so z and every plane
+// base pointer are uniform over a block, and each access is addressed as a
+// scalar base plus a 32-bit in-plane byte offset (the host uses it when
+// nz <= kMaxPlanes and a plane's bytes fit 32 bits).  This takes about
+// three vector instructions per access off the general 64-bit addressing.
+constexpr uint32_t kMaxPlanes = 65535;
+struct PlaneHood {
+    uint32_t p;            // in-plane index y nx + x
+    int32_t ox[3], oy[3];  // in-plane offsets of x - 1, x, x + 1 and y - 1, y, y + 1
+    uint32_t zp[3];        // planes z - 1, z, z + 1; uniform
+};
+
+__device__ __forceinline__ PlaneHood make_plane_hood(uint32_t p, uint32_t z, const Geom &g) {
+    PlaneHood h;
+    h.p = p;
+    const uint32_t y = fdiv(p, g.div_nx), x = p - y * g.nx;
+    const int32_t nx = (int32_t)g.nx, ny = (int32_t)g.ny;
+    h.ox[0] = x == 0 ? nx - 1 : -1;
+    h.ox[1] = 0;
+    h.ox[2] = x == g.nx - 1 ? -(nx - 1) : 1;
+    h.oy[0] = y == 0 ? (ny - 1) * nx : -nx;
+    h.oy[1] = 0;
+    h.oy[2] = y == g.ny - 1 ? -(ny - 1) * nx : nx;
+    h.zp[0] = z == 0 ? g.nz - 1 : z - 1;
+    h.zp[1] = z;
+    h.zp[2] = z == g.nz - 1 ? 0 : z + 1;
+    return h;
+}
+
+// Byte offset of the in-plane neighbour x + s c_q.
+template <typename T>
+__device__ __forceinline__ uint32_t plane_off(const PlaneHood &h, int q, int s) {
+    return (uint32_t)((int32_t)h.p + h.ox[1 + s * kC[q].x] + h.oy[1 + s * kC[q].y]) *
+           (uint32_t)sizeof(T);
+}
+
+// Element at a byte offset from a (uniform) base pointer.
+template <typename T>
+__device__ __forceinline__ T *at_bytes(T *base, uint32_t boff) {
+    return (T *)((char *)base + boff);
 }
 
 // Per-thread neighbourhood of one cell: index offsets of x + dx, y + dy,

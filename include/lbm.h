@@ -172,7 +172,10 @@ int lbm_validate(const lbm_params *p, char *msg, size_t msg_len);
 
 /* Create a context and write the initial state f = f^eq(rho_init, u_init)
  * (no force shift), stored as post-collision data at t = 0.
- *   solid    device uint8 [nz][ny][nx], nonzero = solid; NULL = all fluid
+ *   solid    device uint8 [nz][ny][nx], nonzero = solid; NULL = all fluid.
+ *            Read only during lbm_init, which derives its own per-cell link
+ *            words from it and the walls (4 bytes per cell, freed by
+ *            lbm_destroy); the caller may free or change it afterwards.
  *   pdf0     device state buffer (lbm_state_bytes)
  *   pdf1     second state buffer for TWO_GRID; must be NULL for AA
  *   stream   hipStream_t (NULL = default stream)

@@ -55,12 +55,15 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     const int j = threadIdx.x;
     const uint32_t idx = blockIdx.x * kBlock + j;
     const bool valid = idx < g.ncells;
-    const bool fluid = valid && !(GEN && g.solid && g.solid[idx]);
+    // solid cells exist only where there is a mask (and its link words)
+    const uint32_t link = GEN && valid && g.links ? g.links[idx] : kAllLinks;
+    const bool fluid = valid && !link_solid(link);
     // one hint for every direction: plain unrolled loops suffice
     constexpr bool HL = NT && LBM_NT_ADJ_LOADS != 0, HS = NT && LBM_NT_ADJ_STORES != 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (fluid) {
-        const Hood h = make_hood(idx, g);
+        Hood h = make_hood(idx, g);
+        if (GEN) h.link = g.links ? link : wall_links<QN>(h);
         R d[QN], lam[QN];
 #pragma unroll
         for (int q = 0; q < QN; ++q) {
@@ -99,7 +102,8 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
         // keeping the pull positions live through the collision.
         uint32_t idx2 = idx;
         asm volatile("" : "+v"(idx2));
-        const Hood h = make_hood(idx2, g);
+        Hood h = make_hood(idx2, g);
+        if (GEN) h.link = g.links ? link : wall_links<QN>(h);
 #pragma unroll
         for (int q = 0; q < QN; ++q) {
             if (kC[q].x == 0) continue;
@@ -109,9 +113,19 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
             const int dw = h.ox[1 + kC[q].x];
             const int jw = j + dw;
             if (jw >= 0 && jw < kBlock) {
-                hood_cell<GEN>(h, g, X.q0[q], -1, fl, pos);
-                if (!GEN || (h.vx[1 + kC[q].x] && fl && !(g.solid && g.solid[idx2 + dw])))
-                    st<HS>(lam_prev + q * g.qstride + pos, xbuf[X.rank[q]][j]);
+                hood_cell<false>(h, g, X.q0[q], -1, fl, pos);   // the position only
+                // the writer filled the slot when it is fluid and pulls from a
+                // fluid cell in direction q (its link bit q)
+                bool filled = true;
+                if constexpr (GEN) {
+                    if (g.links) {
+                        const uint32_t wl = g.links[idx2 + dw];
+                        filled = !link_solid(wl) && ((wl >> q) & 1u);
+                    } else {   // walls only: the writer exists and its source is inside
+                        filled = h.vx[1 + kC[q].x] && h.vy[1 - kC[q].y] && h.vz[1 - kC[q].z];
+                    }
+                }
+                if (filled) st<HS>(lam_prev + q * g.qstride + pos, xbuf[X.rank[q]][j]);
             }
             // outbox: this cell's own push that was not parked
             if (fluid) {
@@ -147,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_objective(Geom g, int kind, double i
         double seed[QN];
 #pragma unroll
         for (int q = 0; q < QN; ++q) seed[q] = 0.0;
-        if (!(g.solid && g.solid[idx])) {
+        if (!(g.links && link_solid(g.links[idx]))) {
             double d[QN];
 #pragma unroll
             for (int q = 0; q < QN; ++q)
@@ -189,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_init_vjp(Geom g, const double *__res
     const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= g.ncells) return;
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    if (!(g.solid && g.solid[idx])) {
+    if (!(g.links && link_solid(g.links[idx]))) {
         const double ux = u[idx], uy = u[g.ncells + idx], uz = u[2 * (size_t)g.ncells + idx];
         double cu[NP], E[NP], E0, gE[NP][3];
         Poly::even<double, EQ, NP>(ux, uy, uz, cu, E, E0);

@@ -29,6 +29,7 @@ struct lbm_ctx {
     CollBoth coll;
     Scratch sc;
     uint32_t nblocks;
+    uint32_t *links;   // link words (Geom::links), owned; nullptr when not needed
     std::string err;
 };
 
@@ -374,6 +375,7 @@ extern "C" void lbm_destroy(lbm_ctx *c) {
     if (c->sc.partials) (void)hipFree(c->sc.partials);
     if (c->sc.stage) (void)hipFree(c->sc.stage);
     if (c->sc.result) (void)hipFree(c->sc.result);
+    if (c->links) (void)hipFree(c->links);
     delete c;
 }
 
@@ -410,7 +412,8 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
     for (int d = 0; d < 3; ++d) g.per[d] = p->periodic[d];
     g.qstride = qstride_of(p);
     g.zskip = (int64_t)p->stencil * g.qstride - (int64_t)g.nxy;
-    g.solid = solid;
+    g.links = nullptr;
+    c->links = nullptr;
     c->gen = solid != nullptr || !(p->periodic[0] && p->periodic[1] && p->periodic[2]);
     {
         size_t state_bytes = 0;
@@ -440,6 +443,22 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
     if (e != hipSuccess) {
         lbm_destroy(c);
         return fail(nullptr, LBM_ENOMEM, "scratch allocation: %s", hipGetErrorString(e));
+    }
+    // Link words for the kernels of a lattice with a mask; walls alone are
+    // handled in registers.  The caller's mask is read here only.
+    if (solid) {
+        e = hipMalloc(&c->links, (size_t)g.ncells * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            c->links = nullptr;
+            lbm_destroy(c);
+            return fail(nullptr, LBM_ENOMEM, "link words: %s", hipGetErrorString(e));
+        }
+        g.links = c->links;
+        e = launch_links(g, p->stencil, solid, c->links, c->stream);
+        if (e != hipSuccess) {
+            lbm_destroy(c);
+            return fail(nullptr, LBM_EHIP, "link words: %s", hipGetErrorString(e));
+        }
     }
     const bool q16 = p->dtype == LBM_F16_SHIFTED || p->dtype == LBM_BF16_SHIFTED;
     if (q16) {

@@ -64,7 +64,7 @@ __device__ __forceinline__ void canonical_slot(const Hood &h, const Geom &g, Lay
 __device__ __forceinline__ uint32_t cell_index() { return blockIdx.x * kBlock + threadIdx.x; }
 
 __device__ __forceinline__ bool is_solid(const Geom &g, uint32_t idx) {
-    return g.solid != nullptr && g.solid[idx] != 0;
+    return g.links != nullptr && link_solid(g.links[idx]);
 }
 
 // ---------------------------------------------------------------------------
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Geom g, int compressible, Layou
         shifted_feq<EQ, QN>(r - 1.0, rho0, u[idx], u[g.ncells + idx], u[2 * (size_t)g.ncells + idx],
                         d);
     }
-    const Hood h = make_hood(idx, g);
+    const Hood h = make_hood_links<QN>(idx, g);
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
         int arr;
@@ -128,6 +128,25 @@ template <bool NT>
 __host__ __device__ constexpr bool fwd_load_hint(int cx) { return NT && hint_of(LBM_NT_FWD_LOADS, cx); }
 template <bool NT>
 __host__ __device__ constexpr bool fwd_store_hint(int cx) { return NT && hint_of(LBM_NT_FWD_STORES, cx); }
+
+// Link words (Geom::links) of a lattice with walls or solid cells, from the
+// periodic flags and the caller's mask (nullptr: all fluid).  Built once.
+template <int QN>
+__global__ __launch_bounds__(kBlock) void k_links(Geom g, const uint8_t *__restrict__ solid,
+                                                  uint32_t *__restrict__ links) {
+    const uint32_t idx = cell_index();
+    if (idx >= g.ncells) return;
+    const Hood h = make_hood(idx, g);
+    uint32_t w = solid && solid[idx] ? 1u << kSolidBit : 0u;
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+        const int dx = 1 - kC[q].x, dy = 1 - kC[q].y, dz = 1 - kC[q].z;
+        const bool inside = h.vx[dx] && h.vy[dy] && h.vz[dz];
+        const uint32_t c = (uint32_t)((int32_t)idx + h.ox[dx] + h.oy[dy] + h.oz[dz]);
+        if (inside && !(solid && solid[c])) w |= 1u << q;
+    }
+    links[idx] = w;
+}
 
 // ---------------------------------------------------------------------------
 // Two-grid pull step: dst[q][x] = f*_q(x) from src.
@@ -167,8 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
     } else {
         const uint32_t idx = cell_index();
         if (idx >= g.ncells) return;
-        if (is_solid(g, idx)) return;
-        const Hood h = make_hood(idx, g);
+        const Hood h = make_hood_links<QN>(idx, g);
+        if (link_solid(h.link)) return;
         static_for<QN>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             bool fl;
@@ -234,8 +253,8 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
     }
     const uint32_t idx = cell_index();
     if (idx >= g.ncells) return;
-    if (is_solid(g, idx)) return;
-    const Hood h = make_hood(idx, g);
+    const Hood h = make_hood_links<QN>(idx, g);
+    if (link_solid(h.link)) return;
     static_for<QN>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         bool fl;
@@ -325,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_get(Geom g, Layout layout, double in
     const uint32_t idx = cell_index();
     if (idx >= g.ncells) return;
     const bool solid = is_solid(g, idx);
-    const Hood h = make_hood(idx, g);
+    const Hood h = make_hood_links<QN>(idx, g);
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
         double v = wq(QN, q);
@@ -356,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(Geom g, Layout layout, double
     }
     const uint32_t idx = (uint32_t)c;
     const bool solid = is_solid(g, idx);
-    const Hood h = make_hood(idx, g);
+    const Hood h = make_hood_links<QN>(idx, g);
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
         double v = wq(QN, q);
@@ -379,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_set(Geom g, Layout layout, double s,
     const uint32_t idx = cell_index();
     if (idx >= g.ncells) return;
     const bool solid = is_solid(g, idx);
-    const Hood h = make_hood(idx, g);
+    const Hood h = make_hood_links<QN>(idx, g);
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
         if (solid) {
@@ -410,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Geom g, Layout layout, doubl
     if (idx < g.ncells) {
         double r = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
         if (!is_solid(g, idx)) {
-            const Hood h = make_hood(idx, g);
+            const Hood h = make_hood_links<QN>(idx, g);
             double d[QN];
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
@@ -542,6 +561,16 @@ hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, c
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(sc, cell_blocks(g), 1, 1, sc.result, false, st);
+}
+
+hipError_t launch_links(const Geom &g, int qn, const uint8_t *solid, uint32_t *links,
+                        hipStream_t st) {
+    const dim3 grid(cell_blocks(g)), block(kBlock);
+    if (qn == 27)
+        hipLaunchKernelGGL((k_links<27>), grid, block, 0, st, g, solid, links);
+    else
+        hipLaunchKernelGGL((k_links<19>), grid, block, 0, st, g, solid, links);
+    return hipGetLastError();
 }
 
 hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,

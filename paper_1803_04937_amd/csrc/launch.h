@@ -51,6 +51,9 @@ hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, c
                               const double *u, const Scratch &sc, hipStream_t st);
 // sr: stochastic rounding of the 16-bit stores with the step key `key`;
 // nt: non-temporal hints (false: every access cached).
+// Link words of the lattice (Geom::links) from the walls and the mask.
+hipError_t launch_links(const Geom &g, int qn, const uint8_t *solid, uint32_t *links,
+                        hipStream_t st);
 hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
                           bool sr, bool nt, uint32_t key, const CollBoth &P, const void *src,
                           void *dst, hipStream_t st);

@@ -16,7 +16,9 @@ Also here: a flow driven from rest by a small body force in every storage
 type, which measures how the rounding of the stored f - w treats a per-step
 force increment near its half-ulp (`driven_flow`).
 
-And the forward throughput against the lattice size (`size_sweep`).
+And the forward throughput against the lattice size (`size_sweep`), and one
+checkpointed gradient rollout of the constricted tube with 16-bit storage
+(`tube_rollout`), timed as a whole.
 
 Usage: python -m paper_1803_04937_amd.experiments [--dtype f64] [--sizes 15,25,45]
        python -m paper_1803_04937_amd.experiments --driven-flow
@@ -27,6 +29,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import time
 
 import torch
 
@@ -158,6 +161,40 @@ def size_sweep(sizes=(16, 32, 64, 96, 128, 160, 192, 256, 384), dtypes=("f32", "
     return rows
 
 
+def tube_rollout(steps: int = 2000, dtype: str = "f16s", nx: int = 768, ny: int = 192,
+                 nz: int = 192, omega: float = 1.95, gx: float = 2e-6):
+    """One gradient of the outlet flux J(f_T) through the constricted tube
+    (D3Q19-I TRT, solid mask, periodic box, body force along x), with respect
+    to g_x, omega and the initial velocity, by the checkpointed adjoint:
+    ceil(sqrt(T)) checkpoints, each segment recomputed into a ring before its
+    adjoint steps.  Returns wall times and update counts."""
+    import lbm_inputs
+    from .autograd import RolloutConfig, rollout_objective
+    solid = torch.as_tensor(lbm_inputs.tube_mask(nx, ny, nz, r0=80.0 * ny / 192, depth=0.5,
+                                                 centre=nx / 2, width=60.0 * nx / 768),
+                            dtype=torch.uint8).cuda()
+    rc = RolloutConfig(nx, ny, nz, steps=steps, periodic=(1, 1, 1), collision="trt",
+                       dtype=dtype, objective=1, solid=solid)
+    u = torch.zeros((3, nz, ny, nx), dtype=torch.float64, device="cuda", requires_grad=True)
+    a = torch.tensor([gx, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    w = torch.tensor(omega, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = rollout_objective(u, a, w, rc)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cells = nx * ny * nz
+    fwd, bwd = t1 - t0, t2 - t1
+    return {"shape": [nx, ny, nz], "steps": steps, "dtype": dtype, "segment": rc.segment,
+            "J": J.item(), "dJ/dgx": a.grad[0].item(), "dJ/domega": w.grad.item(),
+            "forward_s": round(fwd, 3), "backward_s": round(bwd, 3),
+            "forward_glups": round(cells * steps / fwd / 1e9, 2),
+            "backward_glups": round(cells * steps / bwd / 1e9, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dtype", default="f64")
@@ -172,7 +209,14 @@ def main():
                     help="only run the forward throughput sweep over lattice sizes")
     ap.add_argument("--mrt", default="",
                     help="omega3,omega4: run the duct study with the MRT collision")
+    ap.add_argument("--tube-rollout", type=int, default=0, metavar="T",
+                    help="only run one checkpointed gradient rollout of T steps through "
+                         "the constricted tube (768 x 192 x 192, --dtype, default f16s)")
     a = ap.parse_args()
+    if a.tube_rollout:
+        dt = a.dtype if a.dtype != "f64" else "f16s"
+        print(json.dumps(tube_rollout(a.tube_rollout, dt)), flush=True)
+        return
     if a.size_sweep:
         for row in size_sweep(policies=("stream", "keep")):
             print(json.dumps(row), flush=True)

@@ -93,6 +93,22 @@ def test_degenerate_shapes_fp64(shape, periodic):
         assert_f64_parity(host(lat.get_pdfs()), f0, f"{shape}")
 
 
+@pytest.mark.parametrize("pattern", ["two_grid", "aa"])
+def test_more_planes_than_planar_launch_fp64(pattern):
+    """A periodic lattice without a mask normally runs the kernels launched
+    one z-plane per grid row; with more planes than that grid dimension
+    allows (65535) it takes the general kernels, whose neighbour links are
+    then formed from the (periodic) walls in registers."""
+    cfg, kw = case(2, 2, 65537, improved=True, trt=True, omega=1.3, accel=(1e-4, 0.0, 2e-4))
+    f0 = _noisy(cfg, 8)
+    lat = lattice(cfg, kw, np.zeros((3,) + cfg.shape), pattern=pattern)
+    lat.set_pdfs(dev(f0))
+    lat.step(2)
+    f0 = oracle.step(cfg, f0, 2)
+    assert_f64_parity(host(lat.get_pdfs()), f0, f"nz = 65537, {pattern}")
+    lat.close()
+
+
 def test_all_solid_domain_is_inert():
     solid = np.ones((4, 5, 6), np.uint8)
     cfg, kw = case(6, 5, 4, solid=solid, accel=(1e-3, 0, 0))

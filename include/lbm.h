@@ -119,6 +119,14 @@ enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
  * Results are identical bit for bit. */
 enum { LBM_CACHE_AUTO = 0, LBM_CACHE_STREAM = 1, LBM_CACHE_KEEP = 2 };
 
+/* What lbm_adjoint_step writes at solid cells.  COPY: lam_t = lam_{t+1}
+ * there (solid cells keep their values through a step).  SKIP: nothing; for
+ * callers that never read lambda at solid cells (fluid cells neither pull
+ * from nor push into solid slots, lbm_objective writes zero there and
+ * lbm_init_vjp returns zero there), it saves 2 Q sizeof(lambda) bytes per
+ * solid cell and step. */
+enum { LBM_ADJ_SOLID_COPY = 0, LBM_ADJ_SOLID_SKIP = 1 };
+
 /* Streaming patterns.  TWO_GRID: pull from one buffer into another.  AA:
  * one buffer updated in place, alternating a step that reads and writes the
  * cell's own slots with a step that reads and writes the neighbours'. */
@@ -150,6 +158,7 @@ typedef struct {
     int32_t rounding;         /* LBM_ROUND_NEAREST / LBM_ROUND_STOCHASTIC          */
     uint32_t seed;            /* key of the stochastic rounding                    */
     int32_t cache_policy;     /* LBM_CACHE_AUTO / STREAM / KEEP                    */
+    int32_t adjoint_solid;    /* LBM_ADJ_SOLID_COPY / SKIP                         */
 } lbm_params;
 
 /* Library version string. */
@@ -271,7 +280,7 @@ int lbm_set_rates(lbm_ctx *c, double omega, const double *accel);
  * Per cell: gather as the forward step, mu = J_C^T lam_next, then write mu_r
  * to lam_prev[r] at x - c_r, or to lam_prev[opposite(r)] at x when x - c_r
  * is a wall or solid (every slot is written exactly once; no atomics).
- * Solid cells copy lam_next through. */
+ * Solid cells copy lam_next through, or are left unwritten (adjoint_solid). */
 int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next, void *lam_prev,
                      double *grad);
 

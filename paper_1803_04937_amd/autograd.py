@@ -45,6 +45,9 @@ class RolloutConfig:
     stencil: int = 19
     mrt_omega3: float = 1.0
     mrt_omega4: float = 1.0
+    # lambda at solid cells is never read here (the objective seeds zero
+    # there, the initial-state VJP ignores it), so the adjoint skips it
+    adjoint_solid: str = "skip"
 
     @property
     def segment(self) -> int:
@@ -63,7 +66,7 @@ class _Rollout(torch.autograd.Function):
                       accel=tuple(float(v) for v in accel.detach().cpu()), scale=cfg.scale,
                       rounding=cfg.rounding, seed=cfg.seed, stencil=cfg.stencil,
                       mrt_omega3=cfg.mrt_omega3, mrt_omega4=cfg.mrt_omega4,
-                      device=u_init.device)
+                      adjoint_solid=cfg.adjoint_solid, device=u_init.device)
         C = cfg.segment
         ckpts = {}
         for t in range(cfg.steps):

@@ -19,6 +19,7 @@ LBM_EQ_STANDARD, LBM_EQ_IMPROVED, LBM_EQ_IMPROVED3 = 0, 1, 2
 LBM_SRT, LBM_TRT, LBM_MRT = 0, 1, 2
 LBM_ROUND_NEAREST, LBM_ROUND_STOCHASTIC = 0, 1
 LBM_CACHE_AUTO, LBM_CACHE_STREAM, LBM_CACHE_KEEP = 0, 1, 2
+LBM_ADJ_SOLID_COPY, LBM_ADJ_SOLID_SKIP = 0, 1
 LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3, 4
 LBM_TWO_GRID, LBM_AA = 0, 1
 LBM_OBJ_KINETIC_ENERGY, LBM_OBJ_OUTLET_FLUX = 0, 1
@@ -55,6 +56,7 @@ class lbm_params(ctypes.Structure):
         ("mrt_omega3", ctypes.c_double), ("mrt_omega4", ctypes.c_double),
         ("rounding", ctypes.c_int32), ("seed", ctypes.c_uint32),
         ("cache_policy", ctypes.c_int32),
+        ("adjoint_solid", ctypes.c_int32),
     ]
 
 
@@ -125,7 +127,7 @@ def make_params(nx, ny, nz, periodic=(1, 1, 1), equilibrium=LBM_EQ_IMPROVED, col
                 dtype=LBM_F32, pattern=LBM_TWO_GRID, compressible=0, adjoint_dtype=None,
                 omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0), scale=0.0,
                 stencil=19, mrt_omega3=1.0, mrt_omega4=1.0, rounding=0,
-                seed=0, cache_policy=0) -> lbm_params:
+                seed=0, cache_policy=0, adjoint_solid=0) -> lbm_params:
     p = lbm_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     for d in range(3):
@@ -148,6 +150,7 @@ def make_params(nx, ny, nz, periodic=(1, 1, 1), equilibrium=LBM_EQ_IMPROVED, col
     p.rounding = int(rounding)
     p.seed = int(seed) & 0xFFFFFFFF
     p.cache_policy = int(cache_policy)
+    p.adjoint_solid = int(adjoint_solid)
     return p
 
 

@@ -26,7 +26,7 @@ struct Lam<LBM_F32> {
 // lam_{t+1}(x), mu = J_C^T lam_{t+1}, push mu_r to lam_t[r][x - c_r] (or to
 // lam_t[rbar][x] when x - c_r is a wall or solid).  Each f_t slot is read by
 // exactly one cell in the forward step, so each lam_t slot is written
-// exactly once.  Solid cells copy lam through.
+// exactly once.  Solid cells copy lam through (copy_solid) or are skipped.
 //
 // Pushes along x would leave every wave's store one element off the
 // 256-byte segments of the array, so two waves write parts of the same
@@ -45,7 +45,7 @@ template <int QN, int DT, int LT, int EQ, bool GEN, bool MRT, bool GRAD, bool NT
 __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     Geom g, Coll<typename Store<DT>::R> P, const typename Store<DT>::T *__restrict__ state,
     const typename Lam<LT>::T *__restrict__ lam_next, typename Lam<LT>::T *__restrict__ lam_prev,
-    double *partials) {
+    double *partials, int copy_solid) {
     using S = Store<DT>;
     using R = typename S::R;
     using L = typename Lam<LT>::T;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
                 st<HS>(p + (fl ? pos : h.pos), (L)lam[q]);
             }
         }
-    } else if (valid) {
+    } else if (valid && copy_solid) {
         const int64_t pos = cell_pos(idx, g);
 #pragma unroll
         for (int q = 0; q < QN; ++q)
@@ -249,8 +249,9 @@ __global__ __launch_bounds__(kBlock) void k_init_vjp(Geom g, const double *__res
 #define LBM_LT_OF(DT) ((DT) == LBM_F64 ? LBM_F64 : LBM_F32)
 
 hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, bool mrt, bool gen,
-                          bool nt, const CollBoth &P, const void *state, const void *lam_next,
-                          void *lam_prev, double *grad, const Scratch &sc, hipStream_t st) {
+                          bool nt, bool copy_solid, const CollBoth &P, const void *state,
+                          const void *lam_next, void *lam_prev, double *grad, const Scratch &sc,
+                          hipStream_t st) {
     const dim3 grid(cell_blocks(g)), block(kBlock);
     const bool want = grad != nullptr;
     if (ltype != (dtype == LBM_F64 ? LBM_F64 : LBM_F32)) return hipErrorInvalidValue;
@@ -262,11 +263,11 @@ hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, b
         if (want)
             hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, true, NT>), grid, block,
                                LBM_ADJ_LDS_BYTES, st, g, pick<DT>(P), (const T *)state,
-                               (const L *)lam_next, (L *)lam_prev, sc.partials);
+                               (const L *)lam_next, (L *)lam_prev, sc.partials, (int)copy_solid);
         else
             hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, false, NT>), grid, block,
                                LBM_ADJ_LDS_BYTES, st, g, pick<DT>(P), (const T *)state,
-                               (const L *)lam_next, (L *)lam_prev, sc.partials);
+                               (const L *)lam_next, (L *)lam_prev, sc.partials, (int)copy_solid);
     })))));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !want) return e;

@@ -151,6 +151,10 @@ static int validate(const lbm_params *p, std::string &why) {
         why = "cache_policy must be LBM_CACHE_AUTO, LBM_CACHE_STREAM or LBM_CACHE_KEEP";
         return LBM_EINVAL;
     }
+    if (p->adjoint_solid != LBM_ADJ_SOLID_COPY && p->adjoint_solid != LBM_ADJ_SOLID_SKIP) {
+        why = "adjoint_solid must be LBM_ADJ_SOLID_COPY or LBM_ADJ_SOLID_SKIP";
+        return LBM_EINVAL;
+    }
     if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC) {
         why = "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC";
         return LBM_EINVAL;
@@ -627,7 +631,8 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam
         return fail(c, LBM_EINVAL, "state_t, lam_next, lam_prev must be set, lam_next != lam_prev");
     hipError_t e = launch_adjoint(c->g, c->p.stencil, c->p.dtype, c->p.adjoint_dtype,
                                   c->p.equilibrium, c->p.collision == LBM_MRT, c->gen, c->adj_nt,
-                                  c->coll, state_t, lam_next, lam_prev, grad, c->sc, c->stream);
+                                  c->p.adjoint_solid == LBM_ADJ_SOLID_COPY, c->coll, state_t,
+                                  lam_next, lam_prev, grad, c->sc, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return LBM_OK;
 }

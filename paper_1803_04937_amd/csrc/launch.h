@@ -71,8 +71,9 @@ hipError_t launch_moments(const Geom &g, int qn, int dtype, Layout layout, doubl
                           int compressible, const double ah[3], const void *A, double *rho,
                           double *u, const Scratch &sc, hipStream_t st);
 hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, bool mrt, bool gen,
-                          bool nt, const CollBoth &P, const void *state, const void *lam_next,
-                          void *lam_prev, double *grad, const Scratch &sc, hipStream_t st);
+                          bool nt, bool copy_solid, const CollBoth &P, const void *state,
+                          const void *lam_next, void *lam_prev, double *grad, const Scratch &sc,
+                          hipStream_t st);
 hipError_t launch_objective(const Geom &g, int qn, int dtype, int ltype, int kind, double inv_s,
                             const double ah[3], const void *state, double *out, void *lam,
                             const Scratch &sc, hipStream_t st);

@@ -19,6 +19,7 @@ PATTERNS = {"two_grid": capi.LBM_TWO_GRID, "aa": capi.LBM_AA}
 ROUNDINGS = {"nearest": capi.LBM_ROUND_NEAREST, "stochastic": capi.LBM_ROUND_STOCHASTIC}
 CACHE_POLICIES = {"auto": capi.LBM_CACHE_AUTO, "stream": capi.LBM_CACHE_STREAM,
                   "keep": capi.LBM_CACHE_KEEP}
+ADJOINT_SOLID = {"copy": capi.LBM_ADJ_SOLID_COPY, "skip": capi.LBM_ADJ_SOLID_SKIP}
 STORAGE_TORCH = {capi.LBM_F64: torch.float64, capi.LBM_F32: torch.float32,
                  capi.LBM_F32_SHIFTED: torch.float32, capi.LBM_F16_SHIFTED: torch.float16,
                  capi.LBM_BF16_SHIFTED: torch.bfloat16}
@@ -41,13 +42,15 @@ class Lattice:
 
     u: initial velocity, tensor (3, nz, ny, nx); rho: optional density
     (nz, ny, nx); solid: optional mask (nz, ny, nx), nonzero = solid.
+    adjoint_solid: "copy" (adjoint_step copies lambda through solid cells)
+    or "skip" (leaves it unwritten there).
     """
 
     def __init__(self, nx, ny, nz, *, u, rho=None, solid=None, periodic=(1, 1, 1),
                  equilibrium="improved", collision="srt", dtype="f32", pattern="two_grid",
                  compressible=False, omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0),
                  scale=0.0, stencil=19, mrt_omega3=1.0, mrt_omega4=1.0, rounding="nearest",
-                 seed=0, cache_policy="auto", device=None, stream=None):
+                 seed=0, cache_policy="auto", adjoint_solid="copy", device=None, stream=None):
         self.device = require_gpu(device)
         self.params = capi.make_params(
             nx, ny, nz, periodic=periodic, equilibrium=_code(EQUILIBRIA, equilibrium),
@@ -56,7 +59,8 @@ class Lattice:
             trt_magic=trt_magic, accel=accel, scale=scale, stencil=stencil,
             mrt_omega3=mrt_omega3, mrt_omega4=mrt_omega4,
             rounding=_code(ROUNDINGS, rounding), seed=seed,
-            cache_policy=_code(CACHE_POLICIES, cache_policy))
+            cache_policy=_code(CACHE_POLICIES, cache_policy),
+            adjoint_solid=_code(ADJOINT_SOLID, adjoint_solid))
         rc, why = capi.lbm_validate(self.params)
         if rc != capi.LBM_OK:
             raise LBMError(rc, why)

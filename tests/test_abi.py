@@ -91,6 +91,7 @@ BAD = [
     (dict(collision=3), "collision"),
     (dict(rounding=2), "rounding"),
     (dict(cache_policy=3), "cache_policy"),
+    (dict(adjoint_solid=2), "adjoint_solid"),
 ]
 
 

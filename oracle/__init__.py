@@ -74,6 +74,8 @@ def _load():
         lib.oracle_moments.argtypes = [cfgp, P, P, P, P]
         lib.oracle_adjoint_step.argtypes = [cfgp, P, P, P, P, P]
         lib.oracle_adjoint_step.restype = ctypes.c_int
+        lib.oracle_adjoint_cells.argtypes = [cfgp, P, P, P, P, ctypes.c_int64, P]
+        lib.oracle_adjoint_cells.restype = ctypes.c_int
         lib.oracle_objective.argtypes = [cfgp, P, ctypes.c_int, P, P, P]
         lib.oracle_objective.restype = ctypes.c_double
         lib.oracle_init_vjp.argtypes = [cfgp, P, P, P, P]
@@ -237,6 +239,23 @@ def adjoint_step(cfg: Config, f_t, lam_next):
     if rc != 0:
         raise ValueError("the oracle adjoint covers the incompressible form only")
     return lam_prev, grad
+
+
+def adjoint_cells(cfg: Config, f_t, lam_next, cells):
+    """mu = J_C^T lam_next at the listed flat cell indices: array (len(cells), Q).
+    mu[k, r] is what adjoint_step pushes to lam_prev[r] at x - c_r (or to
+    lam_prev[rbar] at x when x - c_r is a wall or solid), x = cells[k]."""
+    lib = _load()
+    f_t = _f64(f_t, (cfg.q,) + cfg.shape)
+    lam_next = _f64(lam_next, (cfg.q,) + cfg.shape)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.empty((cells.size, cfg.q))
+    ref, _keep = cfg._c()
+    rc = lib.oracle_adjoint_cells(ref, _ptr(cfg._solid()), _ptr(f_t), _ptr(lam_next),
+                                  _ptr(cells), cells.size, _ptr(out))
+    if rc != 0:
+        raise ValueError("the oracle adjoint covers the incompressible form only")
+    return out
 
 
 def objective(cfg: Config, f, kind: int):

@@ -759,6 +759,40 @@ int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const doubl
     return 0;
 }
 
+/* The adjoint of selected cells only (for sampled checks on large grids):
+ * mu[k * Q + r] = sum_q J_C[q][r] lam_next_q(x) at the fluid cell x =
+ * cells[k], the value oracle_adjoint_step pushes to lam_prev[r][x - c_r]
+ * (or to lam_prev[rbar][x] when x - c_r is a wall or solid).  Solid cells
+ * report lam_next (copied through).  Returns -1 for the compressible form. */
+int oracle_adjoint_cells(const oracle_cfg *cfg, const uint8_t *solid, const double *f_t,
+                         const double *lam_next, const int64_t *cells, int64_t ncell_list,
+                         double *mu_out)
+{
+    if (cfg->compressible) return -1;
+    oracle_prepare();
+    int64_t n = ncells_of(cfg);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < ncell_list; ++k) {
+        int64_t c = cells[k];
+        int x = (int)(c % cfg->nx), y = (int)((c / cfg->nx) % cfg->ny),
+            z = (int)(c / ((int64_t)cfg->nx * cfg->ny));
+        double *mu = mu_out + k * QN(cfg);
+        if (solid && solid[c]) {
+            for (int q = 0; q < QN(cfg); ++q) mu[q] = lam_next[q * n + c];
+            continue;
+        }
+        double g[NQ], J[NQ][NQ], dw[NQ], da[NQ][3];
+        gather(cfg, solid, f_t, x, y, z, g);
+        collision_jacobian(cfg, g, J, dw, da);
+        for (int r = 0; r < QN(cfg); ++r) {
+            double v = 0.0;
+            for (int q = 0; q < QN(cfg); ++q) v += J[q][r] * lam_next[q * n + c];
+            mu[r] = v;
+        }
+    }
+    return 0;
+}
+
 /* Objectives of a stored state and their seeds lam_T = dJ / d f.
  * kind 0: kinetic energy E = 1/2 sum over fluid cells of |u|^2.
  * kind 1: outlet flux, sum of u_x over fluid cells of the plane x = nx - 1.

@@ -113,3 +113,32 @@ def reduced_bound(f_ref, dtype, scale, rounding="nearest"):
     s = scale
     k = 2.0 if rounding == "stochastic" else 1.0
     return k * ulp_half(s * (np.abs(d) + arith), dtype) / s + arith
+
+
+def push_targets(cfg, cells):
+    """Where the adjoint of one pull step writes mu_r of cell x (flat index):
+    slot (r, x - c_r) when that cell is inside (periodic wrap) and fluid,
+    else (rbar, x) (half-way bounce-back).  Returns (direction, cell) index
+    arrays of shape (len(cells), Q), from the definition of the pull."""
+    import oracle
+    c, _, opp = oracle.velocity_set(cfg.stencil)
+    cells = np.asarray(cells, dtype=np.int64)
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    x, y, z = cells % nx, (cells // nx) % ny, cells // (nx * ny)
+    arr = np.empty((cells.size, cfg.q), np.int64)
+    tgt = np.empty((cells.size, cfg.q), np.int64)
+    solid = None if cfg.solid is None else np.asarray(cfg.solid).reshape(-1).astype(bool)
+    for r in range(cfg.q):
+        xs, ys, zs = x - c[r, 0], y - c[r, 1], z - c[r, 2]
+        inside = np.ones(cells.size, bool)
+        for v, n, per in ((xs, nx, cfg.periodic[0]), (ys, ny, cfg.periodic[1]),
+                          (zs, nz, cfg.periodic[2])):
+            if per:
+                v %= n
+            else:
+                inside &= (v >= 0) & (v < n)
+        src = (np.clip(zs, 0, nz - 1) * ny + np.clip(ys, 0, ny - 1)) * nx + np.clip(xs, 0, nx - 1)
+        fluid = inside if solid is None else inside & ~solid[src]
+        arr[:, r] = np.where(fluid, r, opp[r])
+        tgt[:, r] = np.where(fluid, src, cells)
+    return arr, tgt

@@ -1,13 +1,15 @@
 """Parity at full workload sizes, in the launch configurations the benchmark
 times: one GPU step from a stored state against the FP64 oracle evaluated
-cell by cell on a seeded sample (plus every corner and edge cell)."""
+cell by cell on a seeded sample (plus every corner and edge cell); the same
+for one adjoint step, whose sampled cells' pushed values are compared at
+their target slots."""
 import numpy as np
 import pytest
 import torch
 
 import lbm_inputs
 import oracle
-from _helpers import case, host, lattice, reduced_bound
+from _helpers import case, host, lattice, push_targets, reduced_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -80,3 +82,49 @@ def test_tube_192x192x768_f16_walls():
     u0 += rng.uniform(-1e-3, 1e-3, size=u0.shape) * (solid == 0)
     got, want, s = _sampled_step(cfg, kw, u0, "f16s", "two_grid", 4, seed=7)
     assert np.all(np.abs(got - want) <= reduced_bound(want, "f16s", s))
+
+
+def _sampled_adjoint(cfg, kw, u0, dtype, warm, seed):
+    lat = lattice(cfg, kw, u0, dtype=dtype)
+    lat.step(warm)
+    f_in = host(lat.get_pdfs())            # the linearisation point, as stored
+    lam = np.random.default_rng(seed).standard_normal(f_in.shape, dtype=np.float32)
+    ln, lp = lat.new_adjoint(), lat.new_adjoint()
+    lat.state_view(ln).copy_(torch.as_tensor(lam, device="cuda"))
+    grad = torch.zeros(4, dtype=torch.float64, device="cuda")
+    lat.adjoint_step(lat.state, ln, lp, grad)
+    cells = _sample(cfg.shape, seed + 1)
+    if cfg.solid is not None:
+        cells = cells[~np.asarray(cfg.solid).reshape(-1)[cells].astype(bool)]
+    arr, tgt = push_targets(cfg, cells)
+    flat = lat.state_view(lp).reshape(cfg.q, -1)
+    got = host(flat[torch.as_tensor(arr, device="cuda"), torch.as_tensor(tgt, device="cuda")])
+    g = host(grad)
+    lat.close()
+    want = oracle.adjoint_cells(cfg, f_in, lam.astype(np.float64), cells)
+    return got.astype(np.float64), want, g
+
+
+def test_bench_adjoint_256_f32():
+    """The timed adjoint: 256^3 periodic D3Q19-I TRT, omega = 1.8, FP32 state
+    and lambda, at the state after 5 steps."""
+    n = 256
+    cfg, kw = case(n, n, n, improved=True, trt=True, omega=1.8)
+    u0 = lbm_inputs.shear_waves((n, n, n), seed=0)
+    got, want, g = _sampled_adjoint(cfg, kw, u0, "f32", 5, seed=20)
+    assert np.abs(got - want).max() <= 2e-6 * np.abs(want).max()
+    assert np.isfinite(g).all()
+
+
+def test_tube_adjoint_f16_state():
+    """The tube's adjoint at full size: solid mask, walls of the mask next to
+    fluid cells, FP16 state and FP32 lambda, body force."""
+    nx, ny, nz = 768, 192, 192
+    solid = lbm_inputs.tube_mask(nx, ny, nz)
+    cfg, kw = case(nx, ny, nz, periodic=(1, 1, 1), improved=True, trt=True, omega=1.95,
+                   accel=(2e-6, 0, 0), solid=solid)
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = 0.02 * (solid == 0)
+    got, want, g = _sampled_adjoint(cfg, kw, u0, "f16s", 3, seed=21)
+    assert np.abs(got - want).max() <= 2e-6 * np.abs(want).max()
+    assert np.isfinite(g).all()

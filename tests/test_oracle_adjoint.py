@@ -282,3 +282,21 @@ def test_third_order_dfeq_du_against_differences():
             e[b] = 1.0
             fd = _fd4(lambda s: oracle.feq(cfg, 1.0, u + s * e), 1e-4)
             np.testing.assert_allclose(D[:, b], fd, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("cfg", list(_cfgs()) + [c for _, c in _wide_cfgs()],
+                         ids=lambda c: f"Q{c.stencil}I{int(c.improved)}T{int(c.trt)}M{int(c.mrt)}")
+def test_adjoint_cells_match_full_adjoint(cfg):
+    """The per-cell adjoint (for sampled checks of large grids) gives, for
+    every fluid cell, exactly the values the full adjoint pushes to its
+    targets; solid cells report lam_next."""
+    from _helpers import push_targets
+    f = _wstate(cfg, 40)[0]
+    lam = np.random.default_rng(41).standard_normal(f.shape)
+    lp, _ = oracle.adjoint_step(cfg, f, lam)
+    cells = np.arange(cfg.ncells)
+    mu = oracle.adjoint_cells(cfg, f, lam, cells)
+    fluid = ~cfg.solid.reshape(-1).astype(bool)
+    arr, tgt = push_targets(cfg, cells[fluid])
+    np.testing.assert_array_equal(mu[fluid], lp.reshape(cfg.q, -1)[arr, tgt])
+    np.testing.assert_array_equal(mu[~fluid], lam.reshape(cfg.q, -1)[:, ~fluid].T)

@@ -52,7 +52,7 @@ static int hip_fail(lbm_ctx *c, hipError_t e, const char *where) {
     return fail(c, LBM_EHIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-extern "C" const char *lbm_version(void) { return "lbm-d3q19-d3q27-gfx950 1.1"; }
+extern "C" const char *lbm_version(void) { return "lbm-d3q19-d3q27-gfx950 1.2"; }
 
 extern "C" void lbm_velocity_set(int32_t stencil, int32_t *c, double *w, int32_t *o) {
     const int qn = stencil == 27 ? 27 : 19;

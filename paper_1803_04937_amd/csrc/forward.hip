@@ -249,35 +249,35 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Sto
             else
                 S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
         });
-        return;
+    } else {
+        const uint32_t idx = cell_index();
+        if (idx >= g.ncells) return;
+        const Hood h = make_hood_links<QN>(idx, g);
+        if (link_solid(h.link)) return;
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            bool fl;
+            int64_t pos;
+            hood_cell<GEN>(h, g, q, -1, fl, pos);
+            const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
+            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
+                                                                 P.inv_s);
+        });
+        collide<R, EQ, QN, MRT>(d, P);
+        SrBits rb{SR ? mix32(idx ^ key) : 0u};
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr bool H = fwd_store_hint<NT>(kC[q].x);
+            bool fl;
+            int64_t pos;
+            hood_cell<GEN>(h, g, q, +1, fl, pos);
+            typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
+            if constexpr (SR)
+                store_sr<DT, H>(p, fl ? pos : h.pos, d[q], P.s, rb.next(q));
+            else
+                S::template store<H>(p, fl ? pos : h.pos, d[q], (R)wq(QN, q), P.s);
+        });
     }
-    const uint32_t idx = cell_index();
-    if (idx >= g.ncells) return;
-    const Hood h = make_hood_links<QN>(idx, g);
-    if (link_solid(h.link)) return;
-    static_for<QN>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        bool fl;
-        int64_t pos;
-        hood_cell<GEN>(h, g, q, -1, fl, pos);
-        const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
-        d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
-                                                             P.inv_s);
-    });
-    collide<R, EQ, QN, MRT>(d, P);
-    SrBits rb{SR ? mix32(idx ^ key) : 0u};
-    static_for<QN>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr bool H = fwd_store_hint<NT>(kC[q].x);
-        bool fl;
-        int64_t pos;
-        hood_cell<GEN>(h, g, q, +1, fl, pos);
-        typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
-        if constexpr (SR)
-            store_sr<DT, H>(p, fl ? pos : h.pos, d[q], P.s, rb.next(q));
-        else
-            S::template store<H>(p, fl ? pos : h.pos, d[q], (R)wq(QN, q), P.s);
-    });
 }
 
 template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR, bool NT>
@@ -309,27 +309,27 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename St
             else
                 S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
         });
-        return;
+    } else {
+        const uint32_t idx = cell_index();
+        if (idx >= g.ncells) return;
+        if (is_solid(g, idx)) return;
+        const int64_t pos = cell_pos(idx, g);
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            d[q] = S::template load<fwd_load_hint<NT>(0)>(A + q * g.qstride, pos, (R)wq(QN, q),
+                                                          P.inv_s);
+        });
+        collide<R, EQ, QN, MRT>(d, P);
+        SrBits rb{SR ? mix32(idx ^ key) : 0u};
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr bool H = fwd_store_hint<NT>(0);
+            if constexpr (SR)
+                store_sr<DT, H>(A + opp(q) * g.qstride, pos, d[q], P.s, rb.next(q));
+            else
+                S::template store<H>(A + opp(q) * g.qstride, pos, d[q], (R)wq(QN, q), P.s);
+        });
     }
-    const uint32_t idx = cell_index();
-    if (idx >= g.ncells) return;
-    if (is_solid(g, idx)) return;
-    const int64_t pos = cell_pos(idx, g);
-    static_for<QN>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        d[q] = S::template load<fwd_load_hint<NT>(0)>(A + q * g.qstride, pos, (R)wq(QN, q),
-                                                      P.inv_s);
-    });
-    collide<R, EQ, QN, MRT>(d, P);
-    SrBits rb{SR ? mix32(idx ^ key) : 0u};
-    static_for<QN>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr bool H = fwd_store_hint<NT>(0);
-        if constexpr (SR)
-            store_sr<DT, H>(A + opp(q) * g.qstride, pos, d[q], P.s, rb.next(q));
-        else
-            S::template store<H>(A + opp(q) * g.qstride, pos, d[q], (R)wq(QN, q), P.s);
-    });
 }
 
 // ---------------------------------------------------------------------------

@@ -533,10 +533,11 @@ __global__ __launch_bounds__(kBlock) void k_copy(const u32x4 *__restrict__ src,
     } else { constexpr bool SR = false; BODY; }
 
 // Dynamic LDS reserved per stream-collide block (residency cap).
-static constexpr unsigned step_lds_bytes(int qn, int dtype) {
+static constexpr unsigned step_lds_bytes(int qn, int dtype, bool gen) {
     return qn == 27 ? LBM_STEP27_LDS_BYTES
-                    : (dtype == LBM_F32 || dtype == LBM_F32_SHIFTED ? LBM_STEP_LDS_BYTES_4B
-                                                                    : LBM_STEP_LDS_BYTES);
+           : dtype == LBM_F32 || dtype == LBM_F32_SHIFTED ? LBM_STEP_LDS_BYTES_4B
+           : gen && dtype != LBM_F64 ? LBM_STEP_LDS_BYTES_GEN16
+                                     : LBM_STEP_LDS_BYTES;
 }
 
 hipError_t launch_init(const Geom &g, int qn, int dtype, int eq, int compressible, Layout layout,
@@ -584,7 +585,7 @@ hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bo
         LBM_DISPATCH_SR(LBM_DISPATCH_NT({
         using T = typename Store<DT>::T;
         hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
-                           step_lds_bytes(QN, DT), st, g, pick<DT>(P), (const T *)src, (T *)dst, key);
+                           step_lds_bytes(QN, DT, GEN), st, g, pick<DT>(P), (const T *)src, (T *)dst, key);
     }))))));
     return hipGetLastError();
 }
@@ -599,10 +600,10 @@ hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool mrt, bo
         using T = typename Store<DT>::T;
         if (neighbor)
             hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
-                               step_lds_bytes(QN, DT), st, g, pick<DT>(P), (T *)A, key);
+                               step_lds_bytes(QN, DT, GEN), st, g, pick<DT>(P), (T *)A, key);
         else
             hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
-                               step_lds_bytes(QN, DT), st, g, pick<DT>(P), (T *)A, key);
+                               step_lds_bytes(QN, DT, GEN), st, g, pick<DT>(P), (T *)A, key);
     }))))));
     return hipGetLastError();
 }

@@ -101,8 +101,8 @@ __host__ __device__ constexpr bool hint_of(int mode, int cx) { return mode == 2 
 // The hint pays only when the data does not fit the 256 MB last-level cache:
 // the stream-collide and adjoint kernels take NT = false (every access
 // cached) when one step touches at most kCacheResidentBytes, which that
-// cache then serves between steps (forward +12-17 % at 96^3 FP32 and 128^3
-// FP16, adjoint +17-19 % at 96^3; streaming wins from about 310 MB up).
+// cache then serves between steps (forward +10 % at 96^3 FP32 and 128^3
+// FP16, adjoint +2 % at 96^3; streaming wins clearly from about 320 MB up).
 constexpr size_t kCacheResidentBytes = size_t(240) << 20;
 // Occupancy (build-time tuning).  LBM_STEP_LDS_BYTES > 0 reserves that much
 // dynamic LDS per stream-collide block, which caps the resident blocks per

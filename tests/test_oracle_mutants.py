@@ -17,7 +17,14 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_FILES = ["tests/test_oracle_equilibrium.py", "tests/test_oracle_step.py",
-             "tests/test_oracle_adjoint.py", "tests/test_oracle_d3q27.py"]
+             "tests/test_oracle_adjoint.py", "tests/test_oracle_d3q27.py",
+             "tests/test_oracle_cells_compressible.py"]
+
+# The per-cell step's index decoding (the full-size checks' reference).
+_CELLS_DECODE = ("        int x = (int)(c % cfg->nx), y = (int)((c / cfg->nx) % cfg->ny),\n"
+                 "            z = (int)(c / ((int64_t)cfg->nx * cfg->ny));\n"
+                 "        if (solid && solid[c]) {\n"
+                 "            for (int q = 0; q < QN(cfg); ++q) out[k * QN(cfg) + q] = fin[q * n + c];")
 
 MUTANTS = [
     ("standard: 9/2 -> 4", "(3.0 * first + 4.5 * second)", "(3.0 * first + 4.0 * second)"),
@@ -74,6 +81,18 @@ MUTANTS = [
     ("third-order moment derivative drops the power factor",
      "t *= i == d ? pw[i] * ipow(u[i], pw[i] - 1) : ipow(u[i], pw[i]);",
      "t *= i == d ? ipow(u[i], pw[i] - 1) : ipow(u[i], pw[i]);"),
+    ("per-cell step decodes y modulo nx", _CELLS_DECODE,
+     _CELLS_DECODE.replace("(c / cfg->nx) % cfg->ny", "(c / cfg->nx) % cfg->nx")),
+    ("per-cell step decodes z with nx nz", _CELLS_DECODE,
+     _CELLS_DECODE.replace("(int64_t)cfg->nx * cfg->ny", "(int64_t)cfg->nx * cfg->nz")),
+    ("compressible velocity: force shift outside the division",
+     "u[d] = (j[d] + 0.5 * cfg->accel[d]) / *rho0;", "u[d] = j[d] / *rho0 + 0.5 * cfg->accel[d];"),
+    ("compressible flag ignored in the update", "*rho0 = cfg->compressible ? r : 1.0;",
+     "*rho0 = 1.0;"),
+    ("compressible flag ignored in the initial state", "double rho0 = cfg->compressible ? rho : 1.0;",
+     "double rho0 = 1.0;"),
+    ("compressible flag ignored in the read-out", "double rho0 = cfg->compressible ? r : 1.0;",
+     "double rho0 = 1.0;"),
 ]
 
 

@@ -49,6 +49,9 @@ class _Cfg(ctypes.Structure):
         ("stencil", ctypes.c_int),
         ("mrt", ctypes.c_int),
         ("omega3", ctypes.c_double), ("omega4", ctypes.c_double),
+        ("kbc", ctypes.c_int), ("kbc_fixed", ctypes.c_int), ("kbc_gamma", ctypes.c_double),
+        ("open_x", ctypes.c_int), ("rho_out", ctypes.c_double),
+        ("inlet", ctypes.c_void_p),
     ]
 
 
@@ -80,6 +83,8 @@ def _load():
         lib.oracle_objective.restype = ctypes.c_double
         lib.oracle_init_vjp.argtypes = [cfgp, P, P, P, P]
         lib.oracle_init_vjp.restype = ctypes.c_int
+        lib.oracle_kbc_collide.argtypes = [cfgp, P, P]
+        lib.oracle_kbc_collide.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -113,6 +118,11 @@ class Config:
     mrt: bool = False
     omega3: float = 1.0
     omega4: float = 1.0
+    kbc: bool = False          # KBC entropic collision (D3Q19)
+    kbc_gamma: float | None = None   # None: entropic stabiliser; else this fixed value
+    open_x: bool = False       # velocity inlet at x = -1/2, pressure outlet at nx - 1/2
+    rho_out: float = 1.0
+    inlet: np.ndarray | None = field(default=None, repr=False)   # [3, nz, ny]
 
     @property
     def shape(self):
@@ -141,7 +151,19 @@ class Config:
         c.mrt = int(self.mrt)
         c.omega3 = float(self.omega3)
         c.omega4 = float(self.omega4)
-        return ctypes.byref(c), c
+        c.kbc = int(self.kbc)
+        c.kbc_fixed = int(self.kbc_gamma is not None)
+        c.kbc_gamma = 0.0 if self.kbc_gamma is None else float(self.kbc_gamma)
+        c.open_x = int(self.open_x)
+        c.rho_out = float(self.rho_out)
+        keep = None
+        if self.open_x:
+            if self.periodic[0]:
+                raise ValueError("open x faces need a non-periodic x axis")
+            keep = (np.zeros((3, self.nz, self.ny)) if self.inlet is None
+                    else _f64(self.inlet, (3, self.nz, self.ny)))
+            c.inlet = keep.ctypes.data
+        return ctypes.byref(c), (c, keep)
 
     def _solid(self):
         if self.solid is None:
@@ -172,6 +194,17 @@ def feq(cfg: Config, rho: float, u, rho0: float | None = None):
     ref, _keep = cfg._c()
     lib.oracle_feq(ref, float(rho), float(rho0), _ptr(uu), _ptr(out))
     return out
+
+
+def kbc_collide(cfg: Config, g):
+    """(post-collision f*, stabiliser gamma) of the KBC collision of one
+    gathered state g (19 values), without streaming."""
+    lib = _load()
+    gg = _f64(g, (19,))
+    out = np.zeros(19)
+    ref, _keep = cfg._c()
+    gamma = lib.oracle_kbc_collide(ref, _ptr(gg), _ptr(out))
+    return out, gamma
 
 
 def dfeq_du(cfg: Config, u, rho0: float = 1.0):
@@ -237,7 +270,8 @@ def adjoint_step(cfg: Config, f_t, lam_next):
     rc = lib.oracle_adjoint_step(ref, _ptr(cfg._solid()), _ptr(f_t), _ptr(lam_next),
                                  _ptr(lam_prev), _ptr(grad))
     if rc != 0:
-        raise ValueError("the oracle adjoint covers the incompressible form only")
+        raise ValueError("the oracle adjoint covers the incompressible form with SRT, TRT or "
+                         "MRT and without open faces only")
     return lam_prev, grad
 
 

@@ -41,8 +41,25 @@
  *                                  split into even and odd parts over
  *                                  opposite directions is used, with the
  *                                  force (odd) relaxed by omega_minus
+ *   KBC collision ................ Sec. 3.3 (and the Re = 500 runs of
+ *                                  Sec. 5.2): the entropic multi-relaxation
+ *                                  collision of Karlin, Boesch and
+ *                                  Chikatamarla (PRE 90, 031302, 2014; the
+ *                                  KBC-N4 split of Boesch et al., PRE 92,
+ *                                  043309, 2015) written in the 19 kept
+ *                                  moments of Sec. 3.2 with the chosen
+ *                                  equilibrium (Maxwellian moments for
+ *                                  D3Q19-I), as Sec. 3.3 proposes
+ *   inlet, outlet (Sec. 5.2) ..... open x faces: a prescribed inflow
+ *                                  velocity by the moving-wall half-way
+ *                                  bounce-back of Ladd (J. Fluid Mech. 271,
+ *                                  285, 1994) and a constant outlet pressure
+ *                                  by the anti-bounce-back of Ginzburg,
+ *                                  Verhaeghe and d'Humieres (Commun. Comput.
+ *                                  Phys. 3, 427, 2008)
  *   adjoint, objectives .......... not in the paper: the exact transpose of
- *                                  the discrete update above
+ *                                  the discrete update above (SRT, TRT, MRT;
+ *                                  periodic and wall boundaries)
  *
  * Parity pins: the test suite checks these functions against the moment
  * table of Sec. 3.1 (Table 1), an exact-rational moment-matching
@@ -97,6 +114,15 @@ typedef struct {
     int mrt;            /* 1: MRT (D3Q19), overrides trt                     */
     double omega3;      /* MRT rate of the third-order moments               */
     double omega4;      /* MRT rate of the fourth-order moments              */
+    int kbc;            /* 1: KBC entropic collision (D3Q19), overrides the
+                           others                                            */
+    int kbc_fixed;      /* 0: entropic stabiliser; 1: the fixed value
+                           kbc_gamma (for tests of the construction)         */
+    double kbc_gamma;
+    int open_x;         /* 1: inlet at the x = -1/2 face, outlet at x = nx - 1/2
+                           (x must not be periodic); incompressible form     */
+    double rho_out;     /* outlet density                                    */
+    const double *inlet;/* inflow velocity [3][nz][ny] at the inlet cells    */
 } oracle_cfg;
 
 /* Weights by the squared length of c_q (Sec. 2.3).  D3Q19: 1/3, 1/18, 1/36.
@@ -429,17 +455,49 @@ static int is_solid(const uint8_t *solid, int64_t cell)
     return cell < 0 || (solid != NULL && solid[cell] != 0);
 }
 
+static void feq_all(const oracle_cfg *cfg, double rho, double rho0, const double u[3],
+                    double out[NQ]);
+
 /* Pull gather with half-way bounce-back: g_q(x) = f_q(x - c_q), or
- * f_qbar(x) when x - c_q is a wall or a solid cell. */
+ * f_qbar(x) when x - c_q is a wall or a solid cell.  With open x faces, a
+ * source beyond the inlet face (x - c_qx < 0) gives the moving-wall
+ * bounce-back g_q = f_qbar(x) + 6 w_q c_q . u_in (the wall term of a wall
+ * moving at the inflow velocity of the cell's row, rho0 = 1), and a source
+ * beyond the outlet face gives the anti-bounce-back
+ * g_q = -f_qbar(x) + 2 f^eq+_q(rho_out, u_b), with f^eq+ the even part of
+ * the equilibrium, (f^eq_q + f^eq_qbar) / 2, and u_b the velocity of the
+ * cell's own stored state (read-out sum_q c_q f_q(x) - a/2). */
 static void gather(const oracle_cfg *cfg, const uint8_t *solid, const double *f,
                    int x, int y, int z, double g[NQ])
 {
     int64_t n = ncells_of(cfg);
     int64_t here = ((int64_t)z * cfg->ny + y) * cfg->nx + x;
+    double ub[3] = {0.0, 0.0, 0.0}, fe[NQ];
+    int outlet_cell = cfg->open_x && x == cfg->nx - 1;
+    if (outlet_cell) {
+        for (int q = 0; q < QN(cfg); ++q)
+            for (int d = 0; d < 3; ++d) ub[d] += C[q][d] * f[(int64_t)q * n + here];
+        for (int d = 0; d < 3; ++d) ub[d] -= 0.5 * cfg->accel[d];
+        feq_all(cfg, cfg->rho_out, 1.0, ub, fe);
+    }
     for (int q = 0; q < QN(cfg); ++q) {
+        int qb = opposite(q);
+        int px = x - C[q][0];
+        if (cfg->open_x && px < 0) {
+            const double *uin = cfg->inlet;
+            int64_t row = (int64_t)z * cfg->ny + y, nyz = (int64_t)cfg->ny * cfg->nz;
+            double cu = 0.0;
+            for (int d = 0; d < 3; ++d) cu += C[q][d] * uin[d * nyz + row];
+            g[q] = f[(int64_t)qb * n + here] + 6.0 * weight(q) * cu;
+            continue;
+        }
+        if (cfg->open_x && px >= cfg->nx) {
+            g[q] = -f[(int64_t)qb * n + here] + (fe[q] + fe[qb]);
+            continue;
+        }
         int64_t src = shifted_cell(cfg, x, y, z, q, -1);
         if (is_solid(solid, src))
-            g[q] = f[(int64_t)opposite(q) * n + here];
+            g[q] = f[(int64_t)qb * n + here];
         else
             g[q] = f[(int64_t)q * n + src];
     }
@@ -459,12 +517,86 @@ static void macroscopic(const oracle_cfg *cfg, const double g[NQ], double *rho, 
     for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * cfg->accel[d]) / *rho0;
 }
 
+static double monomial(int k, int q);
+
+/* KBC collision of one cell (D3Q19).  The populations split by the 19 kept
+ * monomial moments of Sec. 3.2 (moment k of f: m_k = sum_q M[k][q] f_q,
+ * f_q = sum_k Minv[q][k] m_k) into a kinematic part (orders 0 and 1: mass
+ * and momentum), a shear part s (orders 2 and 3: the stress tensor with its
+ * trace and the third-order moments, the KBC-N4 choice) and a higher-order
+ * part h (order 4).  With beta = omega / 2 and the parts of the
+ * non-equilibrium g - f^eq written ds and dh,
+ *   f*_q = g_q - beta (2 ds_q + gamma dh_q) + force,
+ * so s relaxes at omega (the viscosity) and h at gamma beta.  gamma
+ * minimises the entropy H = sum f ln(f / w) of f* to second order about
+ * f^eq, i.e. the entropic norm <X|X> with <X|Y> = sum_q X_q Y_q / f^eq_q,
+ * over the rates that do not amplify the higher-order part,
+ * 0 <= gamma beta <= 2.  That norm is quadratic in gamma, so the minimiser
+ * is the unconstrained one,
+ *   gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh>,
+ * clamped to [0, 2 / beta]; gamma = 2 (the single-rate value) when
+ * <dh|dh> = 0.  (Unclamped, the rate leaves (0, 2) where dh is small, and
+ * perturbations of the moments that dh barely contains grow from step to
+ * step.)  The force enters
+ * as in the MRT form M^-1 (I - S/2) M F: its kinematic part whole (those
+ * moments are not relaxed), its shear part times (1 - beta), its
+ * higher-order part (zero: F is odd) times (1 - gamma beta / 2).  Returns
+ * gamma. */
+static double kbc_collide(const oracle_cfg *cfg, const double g[NQ], const double fe[NQ],
+                          double out[NQ])
+{
+    double dm[19], mF[19];
+    for (int k = 0; k < 19; ++k) {
+        dm[k] = mF[k] = 0.0;
+        for (int q = 0; q < 19; ++q) {
+            dm[k] += monomial(k, q) * (g[q] - fe[q]);
+            mF[k] += monomial(k, q) * force_term(cfg, q);
+        }
+    }
+    double ds[NQ], dh[NQ], Fk[NQ], Fs[NQ], Fh[NQ];
+    for (int q = 0; q < 19; ++q) {
+        ds[q] = dh[q] = Fk[q] = Fs[q] = Fh[q] = 0.0;
+        for (int k = 0; k < 19; ++k) {
+            int order = Mexp[k][0] + Mexp[k][1] + Mexp[k][2];
+            if (order <= 1) {
+                Fk[q] += Minv[q][k] * mF[k];
+            } else if (order <= 3) {
+                ds[q] += Minv[q][k] * dm[k];
+                Fs[q] += Minv[q][k] * mF[k];
+            } else {
+                dh[q] += Minv[q][k] * dm[k];
+                Fh[q] += Minv[q][k] * mF[k];
+            }
+        }
+    }
+    double beta = 0.5 * cfg->omega, sh = 0.0, hh = 0.0;
+    for (int q = 0; q < 19; ++q) {
+        sh += ds[q] * dh[q] / fe[q];
+        hh += dh[q] * dh[q] / fe[q];
+    }
+    double gamma;
+    if (cfg->kbc_fixed)
+        gamma = cfg->kbc_gamma;
+    else if (hh != 0.0)
+        gamma = fmin(fmax(1.0 / beta - (2.0 - 1.0 / beta) * sh / hh, 0.0), 2.0 / beta);
+    else
+        gamma = 2.0;
+    for (int q = 0; q < 19; ++q)
+        out[q] = g[q] - beta * (2.0 * ds[q] + gamma * dh[q]) + Fk[q] + (1.0 - beta) * Fs[q] +
+                 (1.0 - 0.5 * gamma * beta) * Fh[q];
+    return gamma;
+}
+
 /* Collision of one cell: post-collision f* from the gathered g. */
 static void collide(const oracle_cfg *cfg, const double g[NQ], double out[NQ])
 {
     double rho, rho0, u[3], fe[NQ];
     macroscopic(cfg, g, &rho, &rho0, u);
     feq_all(cfg, rho, rho0, u, fe);
+    if (cfg->kbc) {
+        kbc_collide(cfg, g, fe, out);
+        return;
+    }
     double w = cfg->omega;
     if (cfg->mrt) {
         /* m = M g, m_eq = M f^eq, F moments; relax moment k with its rate. */
@@ -506,6 +638,20 @@ static void collide(const oracle_cfg *cfg, const double g[NQ], double out[NQ])
 /* ------------------------------------------------------------------------ */
 /* Public forward API                                                        */
 /* ------------------------------------------------------------------------ */
+
+/* KBC collision of one gathered state g (no streaming): post-collision
+ * populations and the stabiliser gamma. */
+double oracle_kbc_collide(const oracle_cfg *cfg, const double *g, double *out)
+{
+    oracle_prepare();
+    double rho, rho0, u[3], fe[NQ], gg[NQ], o[NQ];
+    for (int q = 0; q < 19; ++q) gg[q] = g[q];
+    macroscopic(cfg, gg, &rho, &rho0, u);
+    feq_all(cfg, rho, rho0, u, fe);
+    double gamma = kbc_collide(cfg, gg, fe, o);
+    for (int q = 0; q < 19; ++q) out[q] = o[q];
+    return gamma;
+}
 
 /* f = f^eq(rho_init, u_init) in fluid cells, w_q in solid cells.
  * u_init is [3][cells]. */
@@ -606,7 +752,8 @@ void oracle_moments(const oracle_cfg *cfg, const uint8_t *solid, const double *f
 }
 
 /* ------------------------------------------------------------------------ */
-/* Adjoint (exact transpose of oracle_step); incompressible form only.       */
+/* Adjoint (exact transpose of oracle_step); incompressible form, SRT, TRT   */
+/* and MRT, periodic and wall boundaries.                                     */
 /* ------------------------------------------------------------------------ */
 
 /* Full 19x19 Jacobian J[q][r] = d f*_q / d g_r of the collision of one cell,
@@ -711,13 +858,13 @@ static void collision_jacobian(const oracle_cfg *cfg, const double g[NQ], double
 }
 
 /* lam_prev = (d step / d f_t)^T lam_next.  grad[0] += dJ/domega,
- * grad[1..3] += dJ/da (the contribution of this step).  Every stencil,
- * equilibrium and collision of the forward step; returns -1 for the
- * compressible form, which has no adjoint here. */
+ * grad[1..3] += dJ/da (the contribution of this step).  Every stencil and
+ * equilibrium, SRT, TRT and MRT; returns -1 for the compressible form, the
+ * KBC collision and open faces, which have no adjoint here. */
 int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const double *f_t,
                         const double *lam_next, double *lam_prev, double *grad)
 {
-    if (cfg->compressible) return -1;
+    if (cfg->compressible || cfg->kbc || cfg->open_x) return -1;
     oracle_prepare();
     int64_t n = ncells_of(cfg);
     double *plane = (double *)calloc((size_t)cfg->nz * 4, sizeof(double));
@@ -763,12 +910,13 @@ int oracle_adjoint_step(const oracle_cfg *cfg, const uint8_t *solid, const doubl
  * mu[k * Q + r] = sum_q J_C[q][r] lam_next_q(x) at the fluid cell x =
  * cells[k], the value oracle_adjoint_step pushes to lam_prev[r][x - c_r]
  * (or to lam_prev[rbar][x] when x - c_r is a wall or solid).  Solid cells
- * report lam_next (copied through).  Returns -1 for the compressible form. */
+ * report lam_next (copied through).  Returns -1 where oracle_adjoint_step
+ * does. */
 int oracle_adjoint_cells(const oracle_cfg *cfg, const uint8_t *solid, const double *f_t,
                          const double *lam_next, const int64_t *cells, int64_t ncell_list,
                          double *mu_out)
 {
-    if (cfg->compressible) return -1;
+    if (cfg->compressible || cfg->kbc || cfg->open_x) return -1;
     oracle_prepare();
     int64_t n = ncells_of(cfg);
 #pragma omp parallel for schedule(static)

@@ -1,0 +1,367 @@
+"""Pins of the oracle's KBC collision and open (inlet / outlet) faces (CPU).
+
+KBC (Sec. 3.3; used for the Re = 500 runs of Sec. 5.2): the entropic
+multi-relaxation collision of Karlin, Boesch and Chikatamarla with the
+KBC-N4 split, written in the 19 kept moments of Sec. 3.2.  Pinned by: the
+stabiliser fixed at 2 gives SRT; a fixed stabiliser gamma gives MRT with
+second- and third-order rate omega and fourth-order rate gamma omega / 2;
+exact mass and momentum (+ a) conservation; the entropic gamma is the
+minimiser of the second-order entropy found by a line search, and tends to
+the minimiser of the full entropy H = sum f ln(f / w) as the state nears
+equilibrium; the shear viscosity does not depend on gamma (shear-wave decay
+against exp(-nu k^2 t)); the duct projection property of D3Q19-I survives
+(no transverse current), that of D3Q19-S does not.
+
+Open faces (Sec. 5.2: a parabolic inflow profile, a constant-pressure
+outlet): a uniform flow through the faces at any outlet density is a fixed
+point; a fluid at rest at the outlet density is a fixed point; in a
+pressure-driven plane channel the steady mass flux through every cross
+section equals the prescribed inflow sum_y u_in exactly, the profile stays
+the parabolic Poiseuille profile, and the pressure falls linearly with the
+slope 8 nu U / H^2 c_s^-2 of Poiseuille's law.
+"""
+import numpy as np
+import pytest
+
+import lbm_inputs
+import oracle
+
+C, W, OPP = oracle.velocity_set()
+
+
+def _state(cfg, seed, amp=0.02, uamp=0.05):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-uamp, uamp, size=(3,) + cfg.shape)
+    f = oracle.init(cfg, u, rho=1.0 + 0.01 * rng.standard_normal(cfg.shape))
+    f = f + amp * W[:, None, None, None] * rng.standard_normal(f.shape)
+    if cfg.solid is not None:
+        f[:, cfg.solid.astype(bool)] = W[:, None]
+    return f
+
+
+def _box(seed=1):
+    solid = np.zeros((5, 6, 7), np.uint8)
+    solid[2, 2:4, 3] = 1
+    return dict(nx=7, ny=6, nz=5, periodic=(1, 0, 1), solid=solid, accel=(1e-4, -5e-5, 2e-5))
+
+
+# --------------------------------------------------------------------------
+# KBC
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("improved", [0, 1, 2])
+def test_kbc_with_gamma_two_is_srt(improved):
+    base = dict(improved=improved, omega=1.6, **_box())
+    kbc = oracle.Config(kbc=True, kbc_gamma=2.0, **base)
+    srt = oracle.Config(**base)
+    f = _state(srt, 2)
+    np.testing.assert_allclose(oracle.step(kbc, f, 4), oracle.step(srt, f, 4), rtol=0,
+                               atol=2e-15)
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+@pytest.mark.parametrize("gamma", [0.7, 1.3, 3.1])
+def test_kbc_with_fixed_gamma_is_mrt(improved, gamma):
+    """Shear part (orders 2, 3) at omega, higher-order part (order 4) at
+    gamma omega / 2: the MRT of the same moments with those rates."""
+    w = 1.7
+    base = dict(improved=improved, omega=w, **_box())
+    kbc = oracle.Config(kbc=True, kbc_gamma=gamma, **base)
+    mrt = oracle.Config(mrt=True, omega3=w, omega4=gamma * w / 2, **base)
+    f = _state(mrt, 3)
+    np.testing.assert_allclose(oracle.step(kbc, f, 3), oracle.step(mrt, f, 3), rtol=0,
+                               atol=4e-15)
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+def test_kbc_conserves_mass_and_adds_a(improved):
+    a = np.array([1e-3, -2e-3, 5e-4])
+    cfg = oracle.Config(1, 1, 1, improved=improved, kbc=True, omega=1.8, accel=tuple(a))
+    for seed in range(6):
+        f = _state(cfg, 10 + seed, amp=0.08).reshape(19)
+        out, gamma = oracle.kbc_collide(cfg, f)
+        assert abs(out.sum() - f.sum()) < 2e-15
+        np.testing.assert_allclose(C.T @ out - C.T @ f, a, rtol=0, atol=2e-15)
+        assert gamma != 2.0
+
+
+def _quadratic_entropy(cfg, g, gamma):
+    """sum_q (f*_q - f^eq_q)^2 / f^eq_q of the post-collision state at a
+    given stabiliser (f^eq at the state's rho and u; no force)."""
+    c = oracle.Config(1, 1, 1, improved=cfg.improved, kbc=True, kbc_gamma=gamma,
+                      omega=cfg.omega)
+    out, _ = oracle.kbc_collide(c, g)
+    rho, u = g.sum(), C.T @ g
+    fe = oracle.feq(c, rho, u)
+    return np.sum((out - fe) ** 2 / fe)
+
+
+def _golden_min(fn, lo, hi, tol=1e-11):
+    r = (np.sqrt(5) - 1) / 2
+    a, b = lo, hi
+    c, d = b - r * (b - a), a + r * (b - a)
+    fc, fd = fn(c), fn(d)
+    while b - a > tol:
+        if fc < fd:
+            b, d, fd = d, c, fc
+            c = b - r * (b - a)
+            fc = fn(c)
+        else:
+            a, c, fc = c, d, fd
+            d = a + r * (b - a)
+            fd = fn(d)
+    return 0.5 * (a + b)
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+@pytest.mark.parametrize("omega", [1.3, 1.9])
+def test_kbc_gamma_minimises_the_second_order_entropy(improved, omega):
+    """Brute-force line search of the entropic norm of f* - f^eq (evaluated
+    here from the oracle's post-collision states at fixed gamma) over the
+    stable rates 0 <= gamma beta <= 2 finds the oracle's entropic gamma, for
+    minimisers inside the interval and at its ends."""
+    cfg = oracle.Config(1, 1, 1, improved=improved, kbc=True, omega=omega)
+    hi = 2.0 / (omega / 2)
+    rng = np.random.default_rng(20 + improved)
+    inside = 0
+    for _ in range(12):
+        u = rng.uniform(-0.05, 0.05, 3)
+        g = oracle.feq(cfg, 1.0, u) + 0.01 * W * rng.standard_normal(19)
+        _, gamma = oracle.kbc_collide(cfg, g)
+        assert 0.0 <= gamma <= hi
+        best = _golden_min(lambda s: _quadratic_entropy(cfg, g, s), 0.0, hi)
+        assert abs(best - gamma) < 1e-6 * hi, (best, gamma)
+        inside += 1e-3 < gamma < hi - 1e-3
+    assert inside >= 3
+
+
+def test_kbc_gamma_approaches_the_full_entropy_minimiser():
+    """The second-order entropy is the expansion of H = sum f ln(f / w) about
+    f^eq.  At rest f^eq = w rho is the exact minimiser of H for the given
+    mass, so the minimiser of H over gamma approaches the KBC gamma linearly
+    as the non-equilibrium shrinks.  (With a flow, the polynomial f^eq is
+    H's minimiser only to O(u^2), which shifts H's minimiser by about
+    u^2 / |f - f^eq|.)"""
+    w = 1.4
+    cfg = oracle.Config(1, 1, 1, improved=1, kbc=True, omega=w)
+    rng = np.random.default_rng(30)
+    fe = oracle.feq(cfg, 1.0, np.zeros(3))
+    d0 = W * rng.standard_normal(19)
+    d0 -= W * d0.sum() / W.sum()                        # no mass change
+    d0 -= W * 3 * (C @ (C.T @ d0))                      # no momentum either
+    gaps = []
+    for eps in (4e-2, 4e-3):
+        g = fe + eps * d0
+        _, gamma = oracle.kbc_collide(cfg, g)
+        assert 0.0 < gamma < 4 / w            # an interior minimiser
+
+        def H(s):
+            c = oracle.Config(1, 1, 1, improved=1, kbc=True, kbc_gamma=s, omega=w)
+            out, _ = oracle.kbc_collide(c, g)
+            return np.sum(out * np.log(out / W))
+        best = _golden_min(H, gamma - 1, gamma + 1, tol=1e-10)
+        gaps.append(abs(best - gamma))
+    assert gaps[0] < 0.5
+    assert gaps[1] < 0.2 * gaps[0], gaps      # shrinks about linearly (ratio ~ 0.1)
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+def test_kbc_uniform_flow_is_a_fixed_point(improved):
+    cfg = oracle.Config(4, 3, 5, improved=improved, kbc=True, omega=1.6)
+    u = np.zeros((3,) + cfg.shape)
+    u[0], u[1], u[2] = 0.05, -0.03, 0.02
+    f = oracle.init(cfg, u)
+    np.testing.assert_allclose(oracle.step(cfg, f, 20), f, rtol=0, atol=4e-16)
+
+
+def _shear_decay_rate(cfg, n, amp, T):
+    u = lbm_inputs.shear_wave((1, n, 1), amp)
+    f = oracle.init(cfg, u)
+    a0 = oracle.moments(cfg, f)[1][0, 0, :, 0]
+    f = oracle.step(cfg, f, T)
+    a1 = oracle.moments(cfg, f)[1][0, 0, :, 0]
+    s = np.sin(2 * np.pi * np.arange(n) / n)
+    return -np.log((a1 @ s) / (a0 @ s)) / T
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+def test_kbc_shear_viscosity_does_not_depend_on_gamma(improved):
+    """A small-amplitude shear wave decays at the rate nu k^2 of
+    nu = (1/omega - 1/2)/3 whatever the stabiliser: entropic, or fixed at
+    1.2, 2 (SRT) and 3.5; the rates agree with each other to 1e-6 and with
+    the closed form to the lattice's discretisation error."""
+    n, w, T = 32, 1.2, 200
+    nu = (1 / w - 0.5) / 3
+    k = 2 * np.pi / n
+    rates = {}
+    for gamma in (None, 1.2, 2.0, 3.5):
+        cfg = oracle.Config(1, n, 1, improved=improved, kbc=True, kbc_gamma=gamma, omega=w)
+        rates[gamma] = _shear_decay_rate(cfg, n, 1e-4, T)
+    ref = rates[2.0]
+    for gamma, r in rates.items():
+        assert abs(r / ref - 1) < 1e-6, rates
+    # second-order lattice error of the decay rate at k = 2 pi / 32
+    assert abs(ref / (nu * k * k) - 1) < 5e-3, (ref, nu * k * k)
+
+
+def test_kbc_entropic_gamma_differs_from_two_in_a_shear_flow():
+    """Not a no-op: in a developing shear flow the stabiliser departs from
+    the single-rate value and the result differs from SRT."""
+    n = 16
+    base = dict(nx=n, ny=n, nz=1, improved=1, omega=1.95)
+    u = lbm_inputs.taylor_green_2d(n, 0.05)
+    srt = oracle.Config(**base)
+    kbc = oracle.Config(kbc=True, **base)
+    f = oracle.init(srt, u)
+    assert np.abs(oracle.step(kbc, f, 10) - oracle.step(srt, f, 10)).max() > 1e-6
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+def test_kbc_duct_transverse_current(improved):
+    """Duct along x (walls on y and z), driven by a_x from the square-duct
+    Poiseuille field: with the Maxwellian moments (D3Q19-I) KBC keeps u_y =
+    u_z = 0 to rounding, with the standard moments a transverse current
+    develops (Sec. 3.3, Sec. 5.1).  This needs the stabiliser's bound: at
+    the duct centre, where the velocity gradient vanishes, the unbounded
+    rate leaves (0, 2) and rounding noise in the transverse moments grows
+    about 2.5 times per step."""
+    D, w, a = 17, 1.0 / (0.5 + 3 * 0.05), 1e-4
+    nu = (1 / w - 0.5) / 3
+    u = lbm_inputs.duct_poiseuille(1, D, D, a, nu)
+    cfg = oracle.Config(1, D, D, periodic=(1, 0, 0), improved=improved, kbc=True, omega=w,
+                        accel=(a, 0, 0))
+    f = oracle.step(cfg, oracle.init(cfg, u), 400)
+    _, v = oracle.moments(cfg, f)
+    ratio = np.abs(v[1:]).max() / np.abs(v[0]).max()
+    if improved:
+        assert ratio < 1e-13, ratio
+    else:
+        assert ratio > 1e-6, ratio
+
+
+# --------------------------------------------------------------------------
+# Open faces
+# --------------------------------------------------------------------------
+
+def _open_cfg(nx, ny, nz, periodic, **kw):
+    return oracle.Config(nx, ny, nz, periodic=periodic, open_x=True, **kw)
+
+
+COLLISIONS = [dict(), dict(trt=True), dict(kbc=True), dict(mrt=True, omega3=1.5, omega4=1.1)]
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+@pytest.mark.parametrize("coll", COLLISIONS, ids=["srt", "trt", "kbc", "mrt"])
+def test_uniform_flow_through_open_faces_is_a_fixed_point(improved, coll):
+    """f = f^eq(rho_out, U) with inflow U and outlet density rho_out: the
+    moving-wall bounce-back returns f^eq_q (its odd part is 3 w c.U) and the
+    anti-bounce-back returns f^eq_q (twice the even part minus the opposite
+    population), so nothing changes."""
+    nx, ny, nz = 6, 4, 3
+    U = np.array([0.04, 0.01, -0.02])
+    rho_out = 1.02
+    inlet = np.broadcast_to(U[:, None, None], (3, nz, ny)).copy()
+    cfg = _open_cfg(nx, ny, nz, (0, 1, 1), improved=improved, omega=1.4, rho_out=rho_out,
+                    inlet=inlet, **coll)
+    u = np.broadcast_to(U[:, None, None, None], (3, nz, ny, nx)).copy()
+    f = oracle.init(cfg, u, rho=np.full(cfg.shape, rho_out))
+    np.testing.assert_allclose(oracle.step(cfg, f, 15), f, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("coll", COLLISIONS, ids=["srt", "trt", "kbc", "mrt"])
+def test_open_faces_act_on_the_face_cells_only(coll):
+    """One step with open faces equals one step with bounce-back walls on x
+    at every cell that does not touch a face (x = 1 .. nx - 2), and differs
+    from it at both face planes."""
+    nx, ny, nz = 7, 4, 5
+    rng = np.random.default_rng(60)
+    inlet = rng.uniform(-0.03, 0.03, (3, nz, ny))
+    base = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 1, 0), improved=1, omega=1.3,
+                accel=(1e-4, 0, 0), **coll)
+    walls = oracle.Config(**base)
+    op = oracle.Config(open_x=True, rho_out=1.01, inlet=inlet, **base)
+    f = _state(walls, 61)
+    a, b = oracle.step(op, f), oracle.step(walls, f)
+    np.testing.assert_array_equal(a[..., 1:nx - 1], b[..., 1:nx - 1])
+    assert np.abs(a[..., 0] - b[..., 0]).min(axis=0).max() > 0
+    assert np.all(np.abs(a[..., 0] - b[..., 0]).max(axis=0) > 1e-6)
+    assert np.all(np.abs(a[..., nx - 1] - b[..., nx - 1]).max(axis=0) > 1e-6)
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+def test_rest_at_outlet_density_is_a_fixed_point(improved):
+    """Closed inlet (u_in = 0) and walls: the fluid at rest at rho_out stays
+    so; at any other density the outlet moves mass."""
+    nx, ny, nz = 5, 4, 3
+    cfg = _open_cfg(nx, ny, nz, (0, 0, 1), improved=improved, trt=True, omega=1.3,
+                    rho_out=1.05)
+    f = oracle.init(cfg, np.zeros((3,) + cfg.shape), rho=np.full(cfg.shape, 1.05))
+    np.testing.assert_allclose(oracle.step(cfg, f, 10), f, rtol=0, atol=1e-15)
+    f1 = oracle.init(cfg, np.zeros((3,) + cfg.shape))
+    g = oracle.step(cfg, f1, 10)
+    assert g.sum() > f1.sum() + 1e-6      # mass flows in through the outlet
+
+
+def _plane_flux(cfg, f):
+    """Net mass crossing each plane x + 1/2 (x = 0 .. nx - 2) in one step:
+    populations leaving x with c_x = +1 whose destination is fluid, minus
+    those leaving x + 1 with c_x = -1 whose destination is fluid (walls:
+    half-way bounce-back returns a population before it crosses)."""
+    nz, ny, nx = cfg.shape
+    out = np.zeros(nx - 1)
+    for q in range(19):
+        cx, cy, cz = C[q]
+        if cx == 0:
+            continue
+        for y in range(ny):
+            yd = y + cy
+            if not cfg.periodic[1] and not (0 <= yd < ny):
+                continue
+            for z in range(nz):
+                zd = z + cz
+                if not cfg.periodic[2] and not (0 <= zd < nz):
+                    continue
+                if cx > 0:
+                    out += f[q, z, y, :nx - 1]
+                else:
+                    out -= f[q, z, y, 1:]
+    return out
+
+
+def test_pressure_driven_channel():
+    """Plane channel: walls at y = -1/2, H - 1/2, z periodic (one plane),
+    parabolic inflow u_x(y) = 4 U (y + 1/2)(H - 1/2 - y) / H^2 at the inlet,
+    rho_out = 1 at the outlet, no body force, TRT with Lambda = 3/16 (walls
+    exactly at the half-way points).  At steady state: the mass flux through
+    every cross section equals sum_y u_in(y) (the moving-wall term adds
+    6 w_q c_q . u_in per inlet link, u_x per cell); mid-channel the flow is
+    the parabolic profile with no transverse velocity; rho falls linearly
+    with Poiseuille's slope d rho / dx = -3 * 8 nu U / H^2; the linear fit of
+    rho meets rho_out near the outlet face x = nx - 1/2.  (Both face
+    conditions prescribe a velocity or a pressure but not the shear stress,
+    so the profile is disturbed within about H / 2 of each face.)"""
+    H, L, U, w = 12, 40, 0.02, 1.2
+    nu = (1 / w - 0.5) / 3
+    y = np.arange(H)
+    prof = 4 * U * (y + 0.5) * (H - 0.5 - y) / H ** 2
+    inlet = np.zeros((3, 1, H))
+    inlet[0, 0] = prof
+    cfg = _open_cfg(L, H, 1, (0, 0, 1), improved=1, trt=True, omega=w, rho_out=1.0,
+                    inlet=inlet)
+    u0 = np.zeros((3, 1, H, L))
+    u0[0] = prof[None, :, None]
+    f = oracle.init(cfg, u0)
+    f = oracle.step(cfg, f, 20000)
+    f2 = oracle.step(cfg, f, 1)
+    assert np.abs(f2 - f).max() < 1e-12          # steady
+    flux = _plane_flux(cfg, f)
+    np.testing.assert_allclose(flux, prof.sum(), rtol=1e-10, atol=0)
+    rho, u = oracle.moments(cfg, f)
+    mid = slice(L // 2 - 4, L // 2 + 5)
+    np.testing.assert_allclose(u[0, 0, :, L // 2], prof, rtol=0, atol=1e-4 * U)
+    assert np.abs(u[1, 0, :, mid]).max() < 1e-3 * U
+    xs = np.arange(8, L - 8)
+    slope, icpt = np.polyfit(xs, rho[0, H // 2, xs], 1)
+    want = -3 * 8 * nu * U / H ** 2
+    assert abs(slope / want - 1) < 0.01, (slope, want)
+    assert abs((slope * (L - 0.5) + icpt) - 1.0) < 0.05 * abs(want) * L

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_FILES = ["tests/test_oracle_equilibrium.py", "tests/test_oracle_step.py",
              "tests/test_oracle_adjoint.py", "tests/test_oracle_d3q27.py",
-             "tests/test_oracle_cells_compressible.py"]
+             "tests/test_oracle_cells_compressible.py", "tests/test_oracle_kbc_open.py"]
 
 # The per-cell step's index decoding (the full-size checks' reference).
 _CELLS_DECODE = ("        int x = (int)(c % cfg->nx), y = (int)((c / cfg->nx) % cfg->ny),\n"
@@ -93,6 +93,31 @@ MUTANTS = [
      "double rho0 = 1.0;"),
     ("compressible flag ignored in the read-out", "double rho0 = cfg->compressible ? r : 1.0;",
      "double rho0 = 1.0;"),
+    ("KBC shear part takes the fourth order", "} else if (order <= 3) {",
+     "} else if (order <= 4) {"),
+    ("KBC shear part without the third order", "} else if (order <= 3) {",
+     "} else if (order <= 2) {"),
+    ("KBC shear force without (1 - beta)", "+ Fk[q] + (1.0 - beta) * Fs[q] +",
+     "+ Fk[q] + Fs[q] +"),
+    ("KBC stabiliser ratio inverted", "(2.0 - 1.0 / beta) * sh / hh, 0.0)",
+     "(2.0 - 1.0 / beta) * hh / sh, 0.0)"),
+    ("KBC stabiliser sign", "1.0 / beta - (2.0 - 1.0 / beta) * sh / hh",
+     "1.0 / beta + (2.0 - 1.0 / beta) * sh / hh"),
+    ("KBC entropic metric weights w instead of f^eq",
+     "sh += ds[q] * dh[q] / fe[q];\n        hh += dh[q] * dh[q] / fe[q];",
+     "sh += ds[q] * dh[q] / weight(q);\n        hh += dh[q] * dh[q] / weight(q);"),
+    ("KBC stabiliser unbounded", "fmin(fmax(1.0 / beta - (2.0 - 1.0 / beta) * sh / hh, 0.0), 2.0 / beta)",
+     "(1.0 / beta - (2.0 - 1.0 / beta) * sh / hh)"),
+    ("inlet moving-wall term 6 -> 3", "+ 6.0 * weight(q) * cu;", "+ 3.0 * weight(q) * cu;"),
+    ("inlet rule one cell too far", "if (cfg->open_x && px < 0) {", "if (cfg->open_x && px <= 0) {"),
+    ("outlet bounce-back instead of anti-bounce-back",
+     "g[q] = -f[(int64_t)qb * n + here] + (fe[q] + fe[qb]);",
+     "g[q] = f[(int64_t)qb * n + here] + (fe[q] + fe[qb]) - 2.0 * weight(q) * cfg->rho_out;"),
+    ("outlet equilibrium at the inflow density", "feq_all(cfg, cfg->rho_out, 1.0, ub, fe);",
+     "feq_all(cfg, 1.0, 1.0, ub, fe);"),
+    ("outlet velocity from the rest population only",
+     "for (int d = 0; d < 3; ++d) ub[d] += C[q][d] * f[(int64_t)q * n + here];",
+     "for (int d = 0; d < 3; ++d) ub[d] += C[q][d] * f[here];"),
 ]
 
 

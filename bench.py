@@ -113,6 +113,145 @@ def timed_adjoint(torch, lat, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def _rate(ms, cells, bytes_per_cell):
+    gbs = bytes_per_cell * cells / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 5), "mlups": round(cells / (ms * 1e-3) / 1e6, 1),
+            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def timed_fwd_adj(torch, lat, steps, warmup):
+    """Average durations (ms) of one forward step (lbm_stream_collide) and one
+    adjoint step with parameter gradients, alternating as in a rollout."""
+    A, B = lat.buffers
+    lam = [lat.new_adjoint(), lat.new_adjoint()]
+    grad = torch.zeros(4, dtype=torch.float64, device=lat.device)
+    out = torch.zeros(4, dtype=torch.float64, device=lat.device)
+    lat.objective(1, A, out, lam[0])
+    ev = [_events(torch, 3) for _ in range(steps)]
+    for i in range(warmup + steps):
+        src, dst = (A, B) if i % 2 == 0 else (B, A)
+        e = ev[i - warmup] if i >= warmup else None
+        if e:
+            e[0].record()
+        lat.stream_collide(src, dst, i)
+        if e:
+            e[1].record()
+        lat.adjoint_step(src, lam[i % 2], lam[1 - i % 2], grad)
+        if e:
+            e[2].record()
+    torch.cuda.synchronize()
+    if not torch.isfinite(grad).all():
+        raise RuntimeError("non-finite adjoint gradient")
+    return (sum(e[0].elapsed_time(e[1]) for e in ev) / steps,
+            sum(e[1].elapsed_time(e[2]) for e in ev) / steps)
+
+
+def workload_extras(torch, Lattice, lbm_inputs, dev):
+    """The other configured workloads, timed outside the main region."""
+    out = {}
+    # 512^3 periodic D3Q19-I TRT omega = 1.98 in every storage format (the
+    # FP16-storage speedup at its configured size); the rate does not depend
+    # on the field, so these start from seeded noise
+    n = 512
+    cells = n ** 3
+    u = torch.tensor(lbm_inputs.perturbation((n, n, n), seed=3, amp=0.02), device=dev)
+    ms512 = {}
+    for dt, size in (("f32", 4), ("f32s", 4), ("f16s", 2), ("bf16s", 2)):
+        _log(f"extra 512^3 {dt}")
+        lat = Lattice(n, n, n, u=u, equilibrium="improved", collision="trt", omega=1.98,
+                      dtype=dt, device=dev)
+        ms512[dt] = timed_forward(torch, lat, 20, 3)
+        out[f"fwd_512_{dt}_I_trt"] = _rate(ms512[dt], cells, 2 * 19 * size)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    del u
+    torch.cuda.empty_cache()
+    out["fwd_512_f16s_speedup_vs_f32"] = round(ms512["f32"] / ms512["f16s"], 3)
+    # 512 x 128 x 128 duct (walls on y, z), D3Q19-I SRT omega = 1.9, g_x = 1e-6,
+    # FP32 forward + FP32 adjoint
+    nx, ny, nz = 512, 128, 128
+    nu = (1 / 1.9 - 0.5) / 3
+    u = torch.tensor(lbm_inputs.duct_poiseuille(nx, ny, nz, 1e-6, nu), device=dev)
+    _log("extra duct forward + adjoint")
+    lat = Lattice(nx, ny, nz, u=u, periodic=(1, 0, 0), equilibrium="improved",
+                  collision="srt", omega=1.9, accel=(1e-6, 0, 0), dtype="f32", device=dev)
+    fms, ams = timed_fwd_adj(torch, lat, 20, 3)
+    c = nx * ny * nz
+    out["duct_512x128x128_srt_f32"] = {"fwd": _rate(fms, c, 152), "adj": _rate(ams, c, 228),
+                                       "step_mlups": round(c / ((fms + ams) * 1e-3) / 1e6, 1)}
+    lat.close()
+    del lat, u
+    torch.cuda.empty_cache()
+    # 768 x 192 x 192 constricted tube (mask), D3Q19-I TRT omega = 1.95,
+    # FP16 state + FP32 adjoint (lambda at solid cells skipped); bytes per
+    # fluid cell (every cell also reads its 4-byte link word)
+    nx, ny, nz = 768, 192, 192
+    solid = lbm_inputs.tube_mask(nx, ny, nz)
+    nfluid = int((solid == 0).sum())
+    sd = torch.tensor(solid, dtype=torch.uint8, device=dev)
+    u = torch.zeros((3, nz, ny, nx), dtype=torch.float64, device=dev)
+    _log("extra tube forward + adjoint")
+    lat = Lattice(nx, ny, nz, u=u, solid=sd, equilibrium="improved", collision="trt",
+                  omega=1.95, accel=(2e-6, 0, 0), dtype="f16s", adjoint_solid="skip",
+                  device=dev)
+    fms, ams = timed_fwd_adj(torch, lat, 20, 3)
+    c = nx * ny * nz
+    link = 4 * c / nfluid
+    out["tube_768x192x192_trt_f16"] = {
+        "fluid_cells": nfluid, "fwd": _rate(fms, nfluid, 76 + link),
+        "adj": _rate(ams, nfluid, 190 + link),
+        "step_mflups": round(nfluid / ((fms + ams) * 1e-3) / 1e6, 1)}
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    # the same tube opened at both x faces (Sec. 5.2): parabolic inflow at
+    # x = -1/2, constant pressure at x = nx - 1/2, KBC with Maxwellian moments,
+    # FP32 forward
+    _log("extra open tube (KBC)")
+    yc, zc = (ny - 1) / 2, (nz - 1) / 2
+    yy, zz = np.meshgrid(np.arange(ny) - yc, np.arange(nz) - zc)
+    r2 = (yy ** 2 + zz ** 2) / 80.0 ** 2
+    inlet = np.zeros((3, nz, ny))
+    inlet[0] = np.where(r2 < 1, 0.02 * (1 - r2), 0.0)
+    lat = Lattice(nx, ny, nz, u=u, solid=sd, periodic=(0, 1, 1), equilibrium="improved",
+                  collision="kbc", omega=1.98, dtype="f32", open_x=True, rho_out=1.0,
+                  inlet=torch.tensor(inlet, device=dev), device=dev)
+    ms = timed_forward(torch, lat, 20, 3)
+    out["open_tube_768x192x192_kbc_f32"] = _rate(ms, nfluid, 152 + link)
+    lat.close()
+    del lat, u, sd
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_oracle_baseline(lbm_inputs, n, steps=4):
+    """The FP64 oracle timed on the host cores: `steps` forward steps and
+    `steps` adjoint steps of the n^3 bench workload, MLUPS of forward +
+    adjoint cell updates (the unit of the GPU value)."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    _log(f"cpu oracle sample on {cores} threads")
+    cfg = oracle.Config(n, n, n, improved=True, trt=True, omega=1.8, magic=3.0 / 16.0)
+    f = oracle.init(cfg, lbm_inputs.shear_waves((n, n, n), seed=0))
+    t0 = time.perf_counter()
+    g = oracle.step(cfg, f, steps)
+    t_fwd = time.perf_counter() - t0
+    lam = oracle.objective(cfg, g, 0)[1]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lam, _ = oracle.adjoint_step(cfg, f, lam)
+    t_adj = time.perf_counter() - t0
+    cells = n ** 3
+    return {"value": round(steps * cells / (t_fwd + t_adj) / 1e6, 3),
+            "unit": "MLUPS (forward + adjoint)", "cores": cores, "kind": "oracle",
+            "forward_only_mlups": round(steps * cells / t_fwd / 1e6, 3),
+            "adjoint_only_mlups": round(steps * cells / t_adj / 1e6, 3),
+            "sample": f"FP64 C oracle, {n}^3 D3Q19-I TRT: {steps} forward steps "
+                      f"({t_fwd:.1f} s) and {steps} adjoint steps ({t_adj:.1f} s), "
+                      f"{platform.processor() or platform.machine()}"}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -277,6 +416,20 @@ def main():
             lat2.close()
             del lat2
             torch.cuda.empty_cache()
+        # KBC (Sec. 3.3) in the 19 kept moments, 256^3 FP32
+        c = dict(common)
+        c.update(collision="kbc")
+        lat2 = Lattice(n, n, n, u=u0, dtype="f32", **c)
+        msk = timed_forward(torch, lat2, 50, 5)
+        gbs = 2 * 19 * 4 * ncells / (msk * 1e-3) / 1e9
+        extras["fwd_f32_I_kbc"] = {
+            "ms": round(msk, 5), "mlups": round(ncells / (msk * 1e-3) / 1e6, 1),
+            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "time_ratio_vs_trt": round(msk / fwd_ms, 3)}
+        lat2.close()
+        del lat2
+        torch.cuda.empty_cache()
+        extras.update(workload_extras(torch, Lattice, lbm_inputs, dev))
     if copy_ms is not None:
         extras["copy_state_f32"] = {"ms": round(copy_ms, 5), "bytes": 2 * state_bytes,
                                     "GBs": round(2 * state_bytes / (copy_ms * 1e-3) / 1e9, 1)}
@@ -284,19 +437,7 @@ def main():
     # ---- CPU oracle baseline (bounded sample) -----------------------------
     cpu = None
     if not a.no_cpu:
-        import oracle
-        cores = len(os.sched_getaffinity(0))
-        _log(f"cpu oracle sample on {cores} threads")
-        cfg = oracle.Config(n, n, n, improved=True, trt=True, omega=1.8, magic=3.0 / 16.0)
-        f = oracle.init(cfg, u0.cpu().numpy())
-        nsteps = 20
-        t0 = time.perf_counter()
-        oracle.step(cfg, f, nsteps)
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(nsteps * ncells / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
-               "kind": "oracle",
-               "sample": f"FP64 C oracle, forward update only, {n}^3 D3Q19-I TRT, {nsteps} steps "
-                         f"({dt:.1f} s, {platform.processor() or platform.machine()})"}
+        cpu = cpu_oracle_baseline(lbm_inputs, n)
 
     ms_step = step_ms
     out = {

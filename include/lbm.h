@@ -6,9 +6,9 @@
  * an alternative equilibrium discretization" (arXiv:1803.04937).
  *
  * One library call = one or more HIP kernel launches on the caller's stream.
- * All big buffers (PDF states, adjoint fields, checkpoints, moment fields)
- * are caller-owned device memory; the library only allocates a few small
- * scratch buffers (reduction partials) per context.  Pointers are borrowed
+ * All big buffers (PDF states, adjoint fields, checkpoints, moment fields,
+ * link words) are caller-owned device memory; the library only allocates a
+ * few small scratch buffers (reduction partials) per context.  Pointers are borrowed
  * and must outlive the context.  No function throws across the ABI: each
  * returns an lbm_status and lbm_last_error() gives the message.  A context
  * is not thread-safe; several contexts may coexist.  Every call is
@@ -89,8 +89,17 @@ enum { LBM_EQ_STANDARD = 0, LBM_EQ_IMPROVED = 1,
  * e_i in {0,1,2} except the 8 that Sec. 3.2 drops), with m_eq the moments of
  * the chosen equilibrium (for IMPROVED: the Maxwellian ones).  Rates:
  * second-order moments omega, third-order mrt_omega3, fourth-order
- * mrt_omega4 (conserved moments are unaffected by their rate). */
-enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2 };
+ * mrt_omega4 (conserved moments are unaffected by their rate).  KBC (D3Q19
+ * only): the entropically stabilised collision that Sec. 3.3 adapts to the
+ * Maxwellian moments and Sec. 5.2 uses at Re = 500 (Karlin, Boesch and
+ * Chikatamarla 2014, the KBC-N4 split of Boesch et al. 2015), in the same 19
+ * moments: the shear part (second- and third-order moments) relaxes at
+ * omega, the fourth-order part at gamma omega / 2 with the stabiliser gamma
+ * chosen per cell to minimise the entropy of the post-collision state to
+ * second order about f^eq over 0 <= gamma <= 2 (gamma = 2 is SRT; the bound
+ * keeps the fourth-order rate at or below omega).  The force enters as for
+ * MRT. */
+enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2, LBM_KBC = 3 };
 
 /* Storage types of the PDF state. */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2, LBM_F16_SHIFTED = 3,
@@ -159,6 +168,11 @@ typedef struct {
     uint32_t seed;            /* key of the stochastic rounding                    */
     int32_t cache_policy;     /* LBM_CACHE_AUTO / STREAM / KEEP                    */
     int32_t adjoint_solid;    /* LBM_ADJ_SOLID_COPY / SKIP                         */
+    int32_t open_x;           /* 1: open x faces (Sec. 5.2): a velocity inlet at
+                                 x = -1/2 (lbm_set_inlet) and a constant-pressure
+                                 outlet at x = nx - 1/2; needs periodic[0] == 0,
+                                 the two-grid pattern and compressible == 0      */
+    double rho_out;           /* outlet density (open_x), > 0                      */
 } lbm_params;
 
 /* Library version string. */
@@ -179,22 +193,53 @@ int lbm_adjoint_bytes(const lbm_params *p, size_t *bytes);
  * NULL) receives the reason, at most msg_len bytes. */
 int lbm_validate(const lbm_params *p, char *msg, size_t msg_len);
 
-/* Create a context and write the initial state f = f^eq(rho_init, u_init)
- * (no force shift), stored as post-collision data at t = 0.
+/* Bytes of the link-word buffer that lbm_init needs for a lattice with a
+ * solid mask: uint32 [cells] link words followed by uint32
+ * [ceil(cells / 256)] for the list of 256-cell blocks that hold a fluid
+ * cell.  Host only. */
+int lbm_links_bytes(const lbm_params *p, size_t *bytes);
+
+/* Storage scale s that lbm_init picks (scale == 0) for the 16-bit shifted
+ * formats when the largest |f^eq_q - w_q| of the initial state is maxdev:
+ * s = 2^floor(log2(1024 / maxdev)), clamped to [2^-10, 2^14]; 2^14 when
+ * maxdev == 0.  FP16 keeps 11 significant bits whatever s is; s only keeps
+ * s |f - w| inside the format's normal range, and 2^14 does so for every
+ * |f - w| in [2^-28, 4), so a state near rest never gets a scale that the
+ * developing flow would overflow.  Other dtypes: 1.  LBM_EINVAL when
+ * maxdev is negative or not finite.  Host only. */
+int lbm_choose_scale(int32_t dtype, double maxdev, double *scale);
+
+/* Create a context and write the initial state.  The state of the method is
+ * the set of populations f_q(x) of Sec. 2.3; the update of eq.
+ * lb_srt_with_forces maps post-collision populations at t to those at
+ * t + 1.  The initial state is f_q = f^eq_q(rho_init, u_init) of the chosen
+ * equilibrium (eq. discreteEquilibriumStandard, Sec. 2.2, or eq.
+ * new_d3q19_equilibrium, Sec. 3.2), with no force shift, stored as the
+ * post-collision state at t = 0; solid cells hold f_q = w_q.
  *   solid    device uint8 [nz][ny][nx], nonzero = solid; NULL = all fluid.
- *            Read only during lbm_init, which derives its own per-cell link
- *            words from it and the walls (4 bytes per cell, freed by
- *            lbm_destroy); the caller may free or change it afterwards.
- *   pdf0     device state buffer (lbm_state_bytes)
+ *            Read only during lbm_init; the caller may free or change it
+ *            afterwards.
+ *   links    device buffer of lbm_links_bytes bytes, caller-owned, required
+ *            when solid is given (ignored otherwise): lbm_init writes one
+ *            link word per cell into it (bit q: the pull source x - c_q is
+ *            inside and fluid; bit 31: the cell is solid), which every
+ *            kernel of the context reads, and after them the ascending list
+ *            of the 256-cell blocks that hold a fluid cell: the
+ *            stream-collide steps, and the adjoint with adjoint_solid ==
+ *            SKIP, launch only those blocks.  Must outlive the context and
+ *            stay unchanged.
+ *   pdf0     device state buffer (lbm_state_bytes), caller-owned
  *   pdf1     second state buffer for TWO_GRID; must be NULL for AA
  *   stream   hipStream_t (NULL = default stream)
  *   rho_init device double [cells], or NULL for rho = 1
  *   u_init   device double [3][cells]
- * For F16/BF16 storage with scale == 0 the scale is
- * s = 2^floor(log2(1024 / max |f - w|)) over the initial state.
- * On failure *out is NULL. */
-int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid, void *pdf0, void *pdf1,
-             void *stream, const double *rho_init, const double *u_init);
+ * For F16/BF16 storage with scale == 0 the scale is lbm_choose_scale of the
+ * largest |f^eq - w| over the initial state.  The library allocates only
+ * small reduction scratch (about 32 bytes per 256 cells).  On failure *out
+ * is NULL: LBM_EINVAL for invalid parameters or missing buffers, LBM_ENOMEM
+ * when the scratch cannot be allocated, LBM_EHIP for a failed launch. */
+int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid, uint32_t *links,
+             void *pdf0, void *pdf1, void *stream, const double *rho_init, const double *u_init);
 
 /* Release the context's scratch memory (not the caller's buffers). */
 void lbm_destroy(lbm_ctx *c);
@@ -239,8 +284,12 @@ double lbm_scale(const lbm_ctx *c);
  * (mass and momentum); a non-NULL sums synchronises the stream. */
 int lbm_moments(lbm_ctx *c, double *rho, double *u, double *sums);
 
-/* Canonical copy of the current state: device double [Q][cells] (dense,
- * no padding), f*_q in FP64 whatever the dtype and AA parity. */
+/* Canonical copy of the current state: the post-collision populations f*_q
+ * of Sec. 2.3 (the left side of eq. lb_srt_with_forces after the last step)
+ * as device double [Q][cells] (dense, no padding, x fastest), in FP64
+ * whatever the storage dtype and AA parity: dequantised as f = w + d / s
+ * for the shifted formats; solid cells give w_q.  LBM_EINVAL for a NULL
+ * pointer; stream-ordered. */
 int lbm_get_pdfs(lbm_ctx *c, double *canonical);
 
 /* Canonical f*_q (FP64) of the current state at n listed cells: cells is a
@@ -249,8 +298,12 @@ int lbm_get_pdfs(lbm_ctx *c, double *canonical);
  * whole. */
 int lbm_sample_pdfs(lbm_ctx *c, const int64_t *cells, int64_t n, double *out);
 
-/* Overwrite the current state from a canonical device double [Q][cells]
- * (quantised with the context's scale).  Solid cells are set to w_q. */
+/* Overwrite the current state (the populations f*_q of Sec. 2.3, as
+ * lbm_get_pdfs returns them) from a canonical device double [Q][cells]:
+ * stored as f (FP64, FP32) or quantised as RNE(s (f - w)) (shifted formats,
+ * the context's scale), in the layout the context's pattern and step parity
+ * need.  Solid cells are set to w_q.  LBM_EINVAL for a NULL pointer;
+ * stream-ordered. */
 int lbm_set_pdfs(lbm_ctx *c, const double *canonical);
 
 /* Watchdog: FP64 mass of the current state against the mass at lbm_init.
@@ -261,11 +314,27 @@ int lbm_watchdog(lbm_ctx *c, double rel_tol);
 /* Change omega and the body acceleration of an existing context. */
 int lbm_set_rates(lbm_ctx *c, double omega, const double *accel);
 
+/* Inflow velocity of a context with open x faces (Sec. 5.2, where a parabolic
+ * profile is prescribed at the inflow): u_in is a device double [3][nz][ny],
+ * component-major, the velocity of the inlet cell (0, y, z); caller-owned,
+ * borrowed until the next lbm_set_inlet or lbm_destroy, read by every step.
+ * A pull of cell (0, y, z) from beyond the inlet face takes Ladd's
+ * moving-wall half-way bounce-back, g_q = f*_qbar + 6 w_q c_q . u_in(y, z)
+ * (rho0 = 1); a pull of cell (nx-1, y, z) from beyond the outlet face takes
+ * the anti-bounce-back of Ginzburg, Verhaeghe and d'Humieres,
+ * g_q = -f*_qbar + 2 f^eq+_q(rho_out, u_b), with f^eq+ the even part of the
+ * equilibrium and u_b the read-out velocity of the cell's stored state.
+ * lbm_step and lbm_stream_collide return LBM_ESTATE for an open context
+ * until this has been called; LBM_ESTATE for a context without open faces,
+ * LBM_EINVAL for NULL. */
+int lbm_set_inlet(lbm_ctx *c, const double *u_in);
+
 /* ------------------------------------------------------------------------ */
 /* Adjoint (not in the paper): exact transpose of one two-grid step, for    */
-/* every stencil, equilibrium and collision of the forward step.  Adjoint   */
-/* fields hold Q arrays like a state.  Incompressible form                  */
-/* (compressible == 0) only; otherwise LBM_ESTATE.                           */
+/* every stencil and equilibrium and the SRT, TRT and MRT collisions of the */
+/* forward step.  Adjoint fields hold Q arrays like a state.                */
+/* Incompressible form (compressible == 0) without KBC or open faces only;  */
+/* otherwise LBM_ESTATE.                                                    */
 /* ------------------------------------------------------------------------ */
 
 /* lam_prev = (d step / d f_t)^T lam_next for the step f_t -> f_{t+1}.
@@ -280,7 +349,10 @@ int lbm_set_rates(lbm_ctx *c, double omega, const double *accel);
  * Per cell: gather as the forward step, mu = J_C^T lam_next, then write mu_r
  * to lam_prev[r] at x - c_r, or to lam_prev[opposite(r)] at x when x - c_r
  * is a wall or solid (every slot is written exactly once; no atomics).
- * Solid cells copy lam_next through, or are left unwritten (adjoint_solid). */
+ * Solid cells copy lam_next through, or are left unwritten (adjoint_solid).
+ * LBM_ESTATE when state_t is the buffer of an AA context (it holds an AA
+ * layout, not the two-grid one; lbm_stream_collide writes two-grid states
+ * for either pattern). */
 int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next, void *lam_prev,
                      double *grad);
 
@@ -288,7 +360,9 @@ int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next, void
  *   kind  LBM_OBJ_KINETIC_ENERGY: J = 1/2 sum over fluid cells of |u|^2
  *         LBM_OBJ_OUTLET_FLUX:    J = sum of u_x over fluid cells of x = nx-1
  *         with u the stored-state velocity of lbm_moments (rho0 = 1).
- *   state device state buffer of this context
+ *   state device state buffer of this context in the two-grid layout
+ *         (LBM_ESTATE for the buffer of an AA context, which holds an AA
+ *         layout)
  *   out   device double[4]: J and its explicit derivative dJ/da (through
  *         u = sum c f - a/2); written (not accumulated)
  *   lam   device adjoint field (written)                                      */

@@ -530,14 +530,14 @@ static double monomial(int k, int q);
  * so s relaxes at omega (the viscosity) and h at gamma beta.  gamma
  * minimises the entropy H = sum f ln(f / w) of f* to second order about
  * f^eq, i.e. the entropic norm <X|X> with <X|Y> = sum_q X_q Y_q / f^eq_q,
- * over the rates that do not amplify the higher-order part,
- * 0 <= gamma beta <= 2.  That norm is quadratic in gamma, so the minimiser
- * is the unconstrained one,
+ * over 0 <= gamma <= 2: the higher-order part relaxes at most as fast as
+ * the shear part (the stabiliser only adds damping to it).  That norm is
+ * quadratic in gamma, so the minimiser is the unconstrained one,
  *   gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh>,
- * clamped to [0, 2 / beta]; gamma = 2 (the single-rate value) when
- * <dh|dh> = 0.  (Unclamped, the rate leaves (0, 2) where dh is small, and
- * perturbations of the moments that dh barely contains grow from step to
- * step.)  The force enters
+ * clamped to [0, 2]; gamma = 2 (the single-rate value) when <dh|dh> = 0.
+ * (With rates gamma beta up to 2, perturbations of the moments that dh
+ * barely contains grow from step to step where the rate comes close to 2.)
+ * The force enters
  * as in the MRT form M^-1 (I - S/2) M F: its kinematic part whole (those
  * moments are not relaxed), its shear part times (1 - beta), its
  * higher-order part (zero: F is odd) times (1 - gamma beta / 2).  Returns
@@ -578,7 +578,7 @@ static double kbc_collide(const oracle_cfg *cfg, const double g[NQ], const doubl
     if (cfg->kbc_fixed)
         gamma = cfg->kbc_gamma;
     else if (hh != 0.0)
-        gamma = fmin(fmax(1.0 / beta - (2.0 - 1.0 / beta) * sh / hh, 0.0), 2.0 / beta);
+        gamma = fmin(fmax(1.0 / beta - (2.0 - 1.0 / beta) * sh / hh, 0.0), 2.0);
     else
         gamma = 2.0;
     for (int q = 0; q < 19; ++q)

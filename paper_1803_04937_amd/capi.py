@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_EQ_STANDARD, LBM_EQ_IMPROVED, LBM_EQ_IMPROVED3 = 0, 1, 2
-LBM_SRT, LBM_TRT, LBM_MRT = 0, 1, 2
+LBM_SRT, LBM_TRT, LBM_MRT, LBM_KBC = 0, 1, 2, 3
 LBM_ROUND_NEAREST, LBM_ROUND_STOCHASTIC = 0, 1
 LBM_CACHE_AUTO, LBM_CACHE_STREAM, LBM_CACHE_KEEP = 0, 1, 2
 LBM_ADJ_SOLID_COPY, LBM_ADJ_SOLID_SKIP = 0, 1
@@ -30,9 +30,10 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
 # Every entry point declared in include/lbm.h.
 EXPORTS = [
     "lbm_version", "lbm_velocity_set", "lbm_qstride", "lbm_state_bytes", "lbm_adjoint_bytes",
-    "lbm_validate", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_step",
+    "lbm_validate", "lbm_links_bytes", "lbm_choose_scale", "lbm_init", "lbm_destroy", "lbm_last_error", "lbm_step",
     "lbm_stream_collide", "lbm_current_state", "lbm_copy_state", "lbm_time", "lbm_scale", "lbm_moments",
-    "lbm_get_pdfs", "lbm_sample_pdfs", "lbm_set_pdfs", "lbm_watchdog", "lbm_set_rates", "lbm_adjoint_step",
+    "lbm_get_pdfs", "lbm_sample_pdfs", "lbm_set_pdfs", "lbm_watchdog", "lbm_set_rates",
+    "lbm_set_inlet", "lbm_adjoint_step",
     "lbm_objective", "lbm_init_vjp",
 ]
 
@@ -57,6 +58,8 @@ class lbm_params(ctypes.Structure):
         ("rounding", ctypes.c_int32), ("seed", ctypes.c_uint32),
         ("cache_policy", ctypes.c_int32),
         ("adjoint_solid", ctypes.c_int32),
+        ("open_x", ctypes.c_int32),
+        ("rho_out", ctypes.c_double),
     ]
 
 
@@ -75,7 +78,10 @@ def _load():
         "lbm_state_bytes": ([pp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_adjoint_bytes": ([pp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_validate": ([pp, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
-        "lbm_init": ([ctypes.POINTER(P), pp, P, P, P, P, P, P], ctypes.c_int),
+        "lbm_links_bytes": ([pp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_choose_scale": ([ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+                             ctypes.c_int),
+        "lbm_init": ([ctypes.POINTER(P), pp, P, P, P, P, P, P, P], ctypes.c_int),
         "lbm_destroy": ([P], None),
         "lbm_last_error": ([P], ctypes.c_char_p),
         "lbm_step": ([P, ctypes.c_int64], ctypes.c_int),
@@ -90,6 +96,7 @@ def _load():
         "lbm_set_pdfs": ([P, P], ctypes.c_int),
         "lbm_watchdog": ([P, ctypes.c_double], ctypes.c_int),
         "lbm_set_rates": ([P, ctypes.c_double, P], ctypes.c_int),
+        "lbm_set_inlet": ([P, P], ctypes.c_int),
         "lbm_adjoint_step": ([P, P, P, P, P], ctypes.c_int),
         "lbm_objective": ([P, ctypes.c_int, P, P, P], ctypes.c_int),
         "lbm_init_vjp": ([P, P, P, P], ctypes.c_int),
@@ -127,7 +134,7 @@ def make_params(nx, ny, nz, periodic=(1, 1, 1), equilibrium=LBM_EQ_IMPROVED, col
                 dtype=LBM_F32, pattern=LBM_TWO_GRID, compressible=0, adjoint_dtype=None,
                 omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0), scale=0.0,
                 stencil=19, mrt_omega3=1.0, mrt_omega4=1.0, rounding=0,
-                seed=0, cache_policy=0, adjoint_solid=0) -> lbm_params:
+                seed=0, cache_policy=0, adjoint_solid=0, open_x=0, rho_out=1.0) -> lbm_params:
     p = lbm_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     for d in range(3):
@@ -151,6 +158,8 @@ def make_params(nx, ny, nz, periodic=(1, 1, 1), equilibrium=LBM_EQ_IMPROVED, col
     p.seed = int(seed) & 0xFFFFFFFF
     p.cache_policy = int(cache_policy)
     p.adjoint_solid = int(adjoint_solid)
+    p.open_x = int(open_x)
+    p.rho_out = float(rho_out)
     return p
 
 
@@ -196,10 +205,23 @@ def lbm_validate(p: lbm_params):
     return rc, buf.value.decode()
 
 
-def lbm_init(p: lbm_params, solid, pdf0, pdf1, stream, rho_init, u_init) -> int:
+def lbm_links_bytes(p: lbm_params) -> int:
+    v = ctypes.c_size_t()
+    _check(_lib.lbm_links_bytes(ctypes.byref(p), ctypes.byref(v)))
+    return v.value
+
+
+def lbm_choose_scale(dtype: int, maxdev: float) -> float:
+    v = ctypes.c_double()
+    _check(_lib.lbm_choose_scale(int(dtype), float(maxdev), ctypes.byref(v)))
+    return v.value
+
+
+def lbm_init(p: lbm_params, solid, links, pdf0, pdf1, stream, rho_init, u_init) -> int:
     ctx = ctypes.c_void_p()
-    rc = _lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), _addr(solid), _addr(pdf0),
-                       _addr(pdf1), _addr(stream), _addr(rho_init), _addr(u_init))
+    rc = _lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), _addr(solid), _addr(links),
+                       _addr(pdf0), _addr(pdf1), _addr(stream), _addr(rho_init),
+                       _addr(u_init))
     _check(rc, None)
     return ctx.value
 
@@ -268,6 +290,10 @@ def lbm_set_rates(ctx, omega: float, accel=None) -> None:
            ctx)
 
 
+def lbm_set_inlet(ctx, u_in) -> None:
+    _check(_lib.lbm_set_inlet(ctx, _addr(u_in)), ctx)
+
+
 def lbm_adjoint_step(ctx, state_t, lam_next, lam_prev, grad=None) -> None:
     _check(_lib.lbm_adjoint_step(ctx, _addr(state_t), _addr(lam_next), _addr(lam_prev),
                                  _addr(grad)), ctx)
@@ -279,3 +305,4 @@ def lbm_objective(ctx, kind: int, state, out, lam) -> None:
 
 def lbm_init_vjp(ctx, u_init, lam0, grad_u) -> None:
     _check(_lib.lbm_init_vjp(ctx, _addr(u_init), _addr(lam0), _addr(grad_u)), ctx)
+

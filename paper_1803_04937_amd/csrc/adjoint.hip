@@ -52,11 +52,16 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     constexpr const XTab &X = QN == 19 ? kXTab19 : kXTab27;
     // [k][0, kBlock): parked by target cell; [k][kBlock, 2 kBlock): outbox
     __shared__ L xbuf[X.n][2 * kBlock];
+    // the block's link words, for the parked-slot checks after the barrier
+    __shared__ uint32_t lw[GEN ? kBlock : 1];
     const int j = threadIdx.x;
-    const uint32_t idx = blockIdx.x * kBlock + j;
+    // with an active list (solid cells left unwritten) only blocks that hold
+    // a fluid cell are launched
+    const uint32_t idx = gen_block(g) * kBlock + j;
     const bool valid = idx < g.ncells;
     // solid cells exist only where there is a mask (and its link words)
     const uint32_t link = GEN && valid && g.links ? g.links[idx] : kAllLinks;
+    if constexpr (GEN) lw[j] = link;
     const bool fluid = valid && !link_solid(link);
     // one hint for every direction: plain unrolled loops suffice
     constexpr bool HL = NT && LBM_NT_ADJ_LOADS != 0, HS = NT && LBM_NT_ADJ_STORES != 0;
@@ -119,7 +124,7 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
                 bool filled = true;
                 if constexpr (GEN) {
                     if (g.links) {
-                        const uint32_t wl = g.links[idx2 + dw];
+                        const uint32_t wl = lw[jw];
                         filled = !link_solid(wl) && ((wl >> q) & 1u);
                     } else {   // walls only: the writer exists and its source is inside
                         filled = h.vx[1 + kC[q].x] && h.vy[1 - kC[q].y] && h.vz[1 - kC[q].z];
@@ -252,9 +257,14 @@ hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, b
                           bool nt, bool copy_solid, const CollBoth &P, const void *state,
                           const void *lam_next, void *lam_prev, double *grad, const Scratch &sc,
                           hipStream_t st) {
-    const dim3 grid(cell_blocks(g)), block(kBlock);
+    // Solid cells copy lambda through unless it is left unwritten: only then
+    // may the launch skip the blocks without a fluid cell (active list).
+    Geom ga = g;
+    if (copy_solid || !gen) ga.active = nullptr;
+    const dim3 grid(gen_blocks(ga)), block(kBlock);
     const bool want = grad != nullptr;
     if (ltype != (dtype == LBM_F64 ? LBM_F64 : LBM_F32)) return hipErrorInvalidValue;
+    if (grid.x == 0) return hipSuccess;   // every cell solid, nothing written
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(
         LBM_DISPATCH_NT({
         constexpr int LT = LBM_LT_OF(DT);
@@ -262,16 +272,16 @@ hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, b
         using L = typename Lam<LT>::T;
         if (want)
             hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, true, NT>), grid, block,
-                               LBM_ADJ_LDS_BYTES, st, g, pick<DT>(P), (const T *)state,
+                               LBM_ADJ_LDS_BYTES, st, ga, pick<DT>(P), (const T *)state,
                                (const L *)lam_next, (L *)lam_prev, sc.partials, (int)copy_solid);
         else
             hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, false, NT>), grid, block,
-                               LBM_ADJ_LDS_BYTES, st, g, pick<DT>(P), (const T *)state,
+                               LBM_ADJ_LDS_BYTES, st, ga, pick<DT>(P), (const T *)state,
                                (const L *)lam_next, (L *)lam_prev, sc.partials, (int)copy_solid);
     })))));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !want) return e;
-    return launch_finalize(sc, cell_blocks(g), 4, 0, grad, true, st);
+    return launch_finalize(sc, grid.x, 4, 0, grad, true, st);
 }
 
 hipError_t launch_objective(const Geom &g, int qn, int dtype, int ltype, int kind, double inv_s,

@@ -8,6 +8,7 @@
 
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "launch.h"
 #include "lbm.h"
@@ -17,7 +18,8 @@ using namespace lbm;
 struct lbm_ctx {
     lbm_params p;
     Geom g;
-    bool gen;          // walls or solid cells present
+    int gen;           // kGenPeriodic, kGenWalls (walls or solid cells), kGenOpen
+    int co;            // collision operator of the stream-collide kernels (kCo*)
     bool nt;           // stream-collide with non-temporal hints (cache policy)
     bool adj_nt;       // adjoint with non-temporal hints
     void *buf[2];
@@ -29,7 +31,7 @@ struct lbm_ctx {
     CollBoth coll;
     Scratch sc;
     uint32_t nblocks;
-    uint32_t *links;   // link words (Geom::links), owned; nullptr when not needed
+    uint32_t *links;   // link words (Geom::links), caller-owned; nullptr without a mask
     std::string err;
 };
 
@@ -52,7 +54,7 @@ static int hip_fail(lbm_ctx *c, hipError_t e, const char *where) {
     return fail(c, LBM_EHIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-extern "C" const char *lbm_version(void) { return "lbm-d3q19-d3q27-gfx950 1.2"; }
+extern "C" const char *lbm_version(void) { return "lbm-d3q19-d3q27-gfx950 1.3"; }
 
 extern "C" void lbm_velocity_set(int32_t stencil, int32_t *c, double *w, int32_t *o) {
     const int qn = stencil == 27 ? 27 : 19;
@@ -97,7 +99,8 @@ static int validate(const lbm_params *p, std::string &why) {
         why = "unknown equilibrium";
         return LBM_EINVAL;
     }
-    if (p->collision != LBM_SRT && p->collision != LBM_TRT && p->collision != LBM_MRT) {
+    if (p->collision != LBM_SRT && p->collision != LBM_TRT && p->collision != LBM_MRT &&
+        p->collision != LBM_KBC) {
         why = "unknown collision";
         return LBM_EINVAL;
     }
@@ -138,6 +141,32 @@ static int validate(const lbm_params *p, std::string &why) {
         if (!(p->mrt_omega3 > 0.0 && p->mrt_omega3 < 2.0) ||
             !(p->mrt_omega4 > 0.0 && p->mrt_omega4 < 2.0)) {
             why = "mrt_omega3 and mrt_omega4 must lie in (0, 2)";
+            return LBM_EINVAL;
+        }
+    }
+    if (p->collision == LBM_KBC && p->stencil != 19) {
+        why = "KBC is defined for stencil 19 only";
+        return LBM_EINVAL;
+    }
+    if (p->open_x != 0 && p->open_x != 1) {
+        why = "open_x must be 0 or 1";
+        return LBM_EINVAL;
+    }
+    if (p->open_x) {
+        if (p->periodic[0]) {
+            why = "open x faces need periodic[0] == 0";
+            return LBM_EINVAL;
+        }
+        if (p->pattern != LBM_TWO_GRID) {
+            why = "open x faces need the two-grid pattern";
+            return LBM_EINVAL;
+        }
+        if (p->compressible) {
+            why = "open x faces need the incompressible form (compressible == 0)";
+            return LBM_EINVAL;
+        }
+        if (!(p->rho_out > 0.0 && isfinite(p->rho_out))) {
+            why = "rho_out must be a positive finite number";
             return LBM_EINVAL;
         }
     }
@@ -315,6 +344,11 @@ static void set_coll(lbm_ctx *c) {
     d.wp = wp;
     d.wm = wm;
     d.kappa = kappa;
+    // KBC: beta = omega / 2; 1/beta, 2 - 1/beta, upper bound 2 of gamma
+    d.kbc_ib = 2.0 / wp;
+    d.kbc_c = 2.0 - 2.0 / wp;
+    d.kbc_hi = 2.0;
+    d.drho_out = p.open_x ? p.rho_out - 1.0 : 0.0;
     for (int k = 0; k < 3; ++k) d.ah[k] = 0.5 * p.accel[k];
     for (int pp = 0; pp < (p.stencil - 1) / 2; ++pp) {
         const int q = 2 * pp + 1;
@@ -338,6 +372,10 @@ static void set_coll(lbm_ctx *c) {
     f.s = (float)d.s;
     f.inv_s = (float)d.inv_s;
     f.compressible = d.compressible;
+    f.kbc_ib = (float)d.kbc_ib;
+    f.kbc_c = (float)d.kbc_c;
+    f.kbc_hi = (float)d.kbc_hi;
+    f.drho_out = (float)d.drho_out;
     for (int i = 0; i < 100; ++i) f.ke[i] = (float)d.ke[i];
     for (int i = 0; i < 100; ++i) f.pe2[i] = (float)d.pe2[i];
     for (int i = 0; i < 81; ++i) f.ko[i] = (float)d.ko[i];
@@ -379,32 +417,45 @@ extern "C" void lbm_destroy(lbm_ctx *c) {
     if (c->sc.partials) (void)hipFree(c->sc.partials);
     if (c->sc.stage) (void)hipFree(c->sc.stage);
     if (c->sc.result) (void)hipFree(c->sc.result);
-    if (c->links) (void)hipFree(c->links);
     delete c;
 }
 
-extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid, void *pdf0,
-                        void *pdf1, void *stream, const double *rho_init, const double *u_init) {
-    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
-    *out = nullptr;
-    std::string why;
-    if (validate(p, why) != LBM_OK) return fail(nullptr, LBM_EINVAL, "%s", why.c_str());
-    if (!pdf0) return fail(nullptr, LBM_EINVAL, "pdf0 is NULL");
-    if (p->pattern == LBM_TWO_GRID && (!pdf1 || pdf1 == pdf0))
-        return fail(nullptr, LBM_EINVAL, "two-grid needs a second, distinct buffer pdf1");
-    if (p->pattern == LBM_AA && pdf1)
-        return fail(nullptr, LBM_EINVAL, "the AA pattern uses one buffer; pdf1 must be NULL");
-    if (!u_init) return fail(nullptr, LBM_EINVAL, "u_init is NULL");
+// Link-word buffer: one word per cell, then one word per 256-cell block
+// (the list of blocks that hold a fluid cell).
+static size_t links_words(const lbm_params *p) {
+    const size_t n = (size_t)p->nx * p->ny * p->nz;
+    return n + (n + kBlock - 1) / kBlock;
+}
 
-    lbm_ctx *c = new lbm_ctx();
-    c->p = *p;
-    c->buf[0] = pdf0;
-    c->buf[1] = pdf1;
-    c->cur = 0;
-    c->stream = (hipStream_t)stream;
-    c->t = 0;
-    c->scale = 1.0;
-    Geom &g = c->g;
+extern "C" int lbm_links_bytes(const lbm_params *p, size_t *bytes) {
+    std::string why;
+    if (validate(p, why) != LBM_OK || !bytes) return LBM_EINVAL;
+    *bytes = links_words(p) * sizeof(uint32_t);
+    return LBM_OK;
+}
+
+// Scale of the 16-bit formats from the largest |f^eq - w| of the initial
+// state: s = 2^floor(log2(1024 / maxdev)), at most 2^14 and at least 2^-10.
+// FP16 keeps 11 significant bits whatever s is, so s only has to keep
+// s |f - w| below the format's maximum (65504) and above its normal range
+// (2^-14).  2^14 does both for every |f - w| in [2^-28, 4); a larger s,
+// which a state close to rest would ask for, would overflow once the flow
+// develops, so the exponent is capped there (a state at rest gets 2^14).
+extern "C" int lbm_choose_scale(int32_t dtype, double maxdev, double *scale) {
+    if (!scale || !(maxdev >= 0.0) || !isfinite(maxdev)) return LBM_EINVAL;
+    if (dtype != LBM_F16_SHIFTED && dtype != LBM_BF16_SHIFTED) {
+        *scale = 1.0;
+        return LBM_OK;
+    }
+    int ex = maxdev > 0.0 ? (int)floor(log2(1024.0 / maxdev)) : 14;
+    if (ex > 14) ex = 14;
+    if (ex < -10) ex = -10;
+    *scale = ldexp(1.0, ex);
+    return LBM_OK;
+}
+
+// Lattice geometry of validated parameters (no GPU call).
+static void make_geom(const lbm_params *p, const uint32_t *links, Geom &g) {
     g.nx = p->nx;
     g.ny = p->ny;
     g.nz = p->nz;
@@ -416,9 +467,45 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
     for (int d = 0; d < 3; ++d) g.per[d] = p->periodic[d];
     g.qstride = qstride_of(p);
     g.zskip = (int64_t)p->stencil * g.qstride - (int64_t)g.nxy;
-    g.links = nullptr;
+    g.links = links;
+    g.inlet = nullptr;
+    g.active = nullptr;
+    g.nactive = 0;
+}
+
+extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid, uint32_t *links,
+                        void *pdf0, void *pdf1, void *stream, const double *rho_init,
+                        const double *u_init) {
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (validate(p, why) != LBM_OK) return fail(nullptr, LBM_EINVAL, "%s", why.c_str());
+    if (!pdf0) return fail(nullptr, LBM_EINVAL, "pdf0 is NULL");
+    if (p->pattern == LBM_TWO_GRID && (!pdf1 || pdf1 == pdf0))
+        return fail(nullptr, LBM_EINVAL, "two-grid needs a second, distinct buffer pdf1");
+    if (p->pattern == LBM_AA && pdf1)
+        return fail(nullptr, LBM_EINVAL, "the AA pattern uses one buffer; pdf1 must be NULL");
+    if (!u_init) return fail(nullptr, LBM_EINVAL, "u_init is NULL");
+    if (solid && !links)
+        return fail(nullptr, LBM_EINVAL,
+                    "a solid mask needs a link-word buffer of lbm_links_bytes bytes");
+
+    lbm_ctx *c = new lbm_ctx();
+    c->p = *p;
+    c->buf[0] = pdf0;
+    c->buf[1] = pdf1;
+    c->cur = 0;
+    c->stream = (hipStream_t)stream;
+    c->t = 0;
+    c->scale = 1.0;
+    Geom &g = c->g;
+    make_geom(p, nullptr, g);
     c->links = nullptr;
-    c->gen = solid != nullptr || !(p->periodic[0] && p->periodic[1] && p->periodic[2]);
+    c->gen = p->open_x ? kGenOpen
+             : (solid != nullptr || !(p->periodic[0] && p->periodic[1] && p->periodic[2]))
+                 ? kGenWalls
+                 : kGenPeriodic;
+    c->co = p->collision == LBM_MRT ? kCoMrt : p->collision == LBM_KBC ? kCoKbc : kCoPair;
     {
         size_t state_bytes = 0;
         lbm_state_bytes(p, &state_bytes);
@@ -440,6 +527,7 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
             return fail(nullptr, LBM_EINVAL, "internal: fast division check failed");
         }
     c->nblocks = cell_blocks(g);
+
     c->sc.stage_half = (size_t)((c->nblocks + kReduceChunk - 1) / kReduceChunk) * 4;
     hipError_t e = hipMalloc(&c->sc.partials, (size_t)c->nblocks * 4 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->sc.stage, 2 * c->sc.stage_half * sizeof(double));
@@ -448,20 +536,41 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
         lbm_destroy(c);
         return fail(nullptr, LBM_ENOMEM, "scratch allocation: %s", hipGetErrorString(e));
     }
-    // Link words for the kernels of a lattice with a mask; walls alone are
-    // handled in registers.  The caller's mask is read here only.
+    // Link words for the kernels of a lattice with a mask, written into the
+    // caller's buffer; walls alone are handled in registers.  The caller's
+    // mask is read here only.
     if (solid) {
-        e = hipMalloc(&c->links, (size_t)g.ncells * sizeof(uint32_t));
-        if (e != hipSuccess) {
-            c->links = nullptr;
-            lbm_destroy(c);
-            return fail(nullptr, LBM_ENOMEM, "link words: %s", hipGetErrorString(e));
-        }
+        c->links = links;
         g.links = c->links;
         e = launch_links(g, p->stencil, solid, c->links, c->stream);
         if (e != hipSuccess) {
             lbm_destroy(c);
             return fail(nullptr, LBM_EHIP, "link words: %s", hipGetErrorString(e));
+        }
+        // The blocks that hold a fluid cell, listed in ascending order after
+        // the link words: the kernels that skip solid cells launch only
+        // those.  The flags go through the host once, at set-up.
+        uint32_t *list = c->links + g.ncells;
+        const uint32_t nb = c->nblocks;
+        std::vector<uint32_t> flags(nb);
+        e = launch_block_fluid(g, list, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(flags.data(), list, nb * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        uint32_t na = 0;
+        for (uint32_t b = 0; b < nb; ++b)
+            if (flags[b]) flags[na++] = b;
+        if (e == hipSuccess && na < nb) {
+            e = hipMemcpyAsync(list, flags.data(), na * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            g.active = list;
+            g.nactive = na;
+        }
+        if (e != hipSuccess) {
+            lbm_destroy(c);
+            return fail(nullptr, LBM_EHIP, "active blocks: %s", hipGetErrorString(e));
         }
     }
     const bool q16 = p->dtype == LBM_F16_SHIFTED || p->dtype == LBM_BF16_SHIFTED;
@@ -480,10 +589,7 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
                 lbm_destroy(c);
                 return fail(nullptr, LBM_EHIP, "scale search: %s", hipGetErrorString(e));
             }
-            int ex = maxdev > 0.0 ? (int)floor(log2(1024.0 / maxdev)) : 14;
-            if (ex > 40) ex = 40;
-            if (ex < -10) ex = -10;
-            c->scale = ldexp(1.0, ex);
+            lbm_choose_scale(p->dtype, maxdev, &c->scale);
         }
     }
     set_coll(c);
@@ -509,22 +615,37 @@ extern "C" const char *lbm_last_error(const lbm_ctx *c) {
     return c ? c->err.c_str() : g_init_error.c_str();
 }
 
+static int need_inlet(lbm_ctx *c) {
+    if (c->p.open_x && !c->g.inlet)
+        return fail(c, LBM_ESTATE, "open x faces: set the inflow with lbm_set_inlet first");
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_inlet(lbm_ctx *c, const double *u_in) {
+    if (!c) return LBM_EINVAL;
+    if (!c->p.open_x) return fail(c, LBM_ESTATE, "the context has no open faces");
+    if (!u_in) return fail(c, LBM_EINVAL, "u_in is NULL");
+    c->g.inlet = u_in;
+    return LBM_OK;
+}
+
 extern "C" int lbm_step(lbm_ctx *c, int64_t n) {
     if (!c) return LBM_EINVAL;
     if (n < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    if (need_inlet(c) != LBM_OK) return LBM_ESTATE;
     for (int64_t i = 0; i < n; ++i) {
         hipError_t e;
         if (c->p.pattern == LBM_TWO_GRID) {
-            e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                               c->p.collision == LBM_MRT, c->gen, sr(c), c->nt,
+            e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->co,
+                               c->gen, sr(c), c->nt,
                                step_key(c->p.seed, c->t), c->coll, c->buf[c->cur],
                                c->buf[1 - c->cur], c->stream);
             if (e == hipSuccess) c->cur ^= 1;
         } else {
             // even step count: the state is in local layout, so the next step
             // is a neighbour step; odd: a local step.
-            e = launch_step_aa(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                               c->p.collision == LBM_MRT, c->gen, sr(c), c->nt,
+            e = launch_step_aa(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->co,
+                               c->gen != kGenPeriodic, sr(c), c->nt,
                                step_key(c->p.seed, c->t), (c->t & 1) == 0, c->coll, c->buf[0],
                                c->stream);
         }
@@ -538,8 +659,9 @@ extern "C" int lbm_stream_collide(lbm_ctx *c, const void *src, void *dst, int64_
     if (!c) return LBM_EINVAL;
     if (!src || !dst || src == dst) return fail(c, LBM_EINVAL, "src and dst must be distinct buffers");
     if (t < 0) return fail(c, LBM_EINVAL, "t must be >= 0");
-    hipError_t e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium,
-                                  c->p.collision == LBM_MRT, c->gen, sr(c), c->nt,
+    if (need_inlet(c) != LBM_OK) return LBM_ESTATE;
+    hipError_t e = launch_step_tg(c->g, c->p.stencil, c->p.dtype, c->p.equilibrium, c->co,
+                                  c->gen, sr(c), c->nt,
                                   step_key(c->p.seed, t), c->coll, src, dst, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "stream_collide");
     return LBM_OK;
@@ -622,15 +744,28 @@ extern "C" int lbm_set_rates(lbm_ctx *c, double omega, const double *accel) {
     return LBM_OK;
 }
 
+// The adjoint family covers the incompressible form with SRT, TRT and MRT
+// and without open faces.
+static int adjoint_ok(lbm_ctx *c) {
+    if (c->p.compressible)
+        return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
+    if (c->p.collision == LBM_KBC || c->p.open_x)
+        return fail(c, LBM_ESTATE, "the adjoint covers SRT, TRT and MRT without open faces");
+    return LBM_OK;
+}
+
 extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam_next,
                                 void *lam_prev, double *grad) {
     if (!c) return LBM_EINVAL;
-    if (c->p.compressible)
-        return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
+    if (adjoint_ok(c) != LBM_OK) return LBM_ESTATE;
     if (!state_t || !lam_next || !lam_prev || lam_next == lam_prev)
         return fail(c, LBM_EINVAL, "state_t, lam_next, lam_prev must be set, lam_next != lam_prev");
+    if (c->p.pattern == LBM_AA && state_t == c->buf[0])
+        return fail(c, LBM_ESTATE, "the AA buffer holds an AA layout; pass a state in the "
+                                   "two-grid layout (lbm_stream_collide writes one)");
     hipError_t e = launch_adjoint(c->g, c->p.stencil, c->p.dtype, c->p.adjoint_dtype,
-                                  c->p.equilibrium, c->p.collision == LBM_MRT, c->gen, c->adj_nt,
+                                  c->p.equilibrium, c->p.collision == LBM_MRT,
+                                  c->gen != kGenPeriodic, c->adj_nt,
                                   c->p.adjoint_solid == LBM_ADJ_SOLID_COPY, c->coll, state_t,
                                   lam_next, lam_prev, grad, c->sc, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
@@ -639,11 +774,13 @@ extern "C" int lbm_adjoint_step(lbm_ctx *c, const void *state_t, const void *lam
 
 extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *out, void *lam) {
     if (!c) return LBM_EINVAL;
-    if (c->p.compressible)
-        return fail(c, LBM_ESTATE, "objectives are defined for the incompressible form only");
+    if (adjoint_ok(c) != LBM_OK) return LBM_ESTATE;
     if (kind != LBM_OBJ_KINETIC_ENERGY && kind != LBM_OBJ_OUTLET_FLUX)
         return fail(c, LBM_EINVAL, "unknown objective kind %d", kind);
     if (!state || !out || !lam) return fail(c, LBM_EINVAL, "state, out and lam must be set");
+    if (c->p.pattern == LBM_AA && state == c->buf[0])
+        return fail(c, LBM_ESTATE, "the AA buffer holds an AA layout; pass a state in the "
+                                   "two-grid layout (lbm_stream_collide writes one)");
     hipError_t e = launch_objective(c->g, c->p.stencil, c->p.dtype, c->p.adjoint_dtype, kind,
                                     1.0 / c->scale, c->coll.d.ah, state, out, lam, c->sc,
                                     c->stream);
@@ -653,8 +790,7 @@ extern "C" int lbm_objective(lbm_ctx *c, int kind, const void *state, double *ou
 
 extern "C" int lbm_init_vjp(lbm_ctx *c, const double *u_init, const void *lam0, double *grad_u) {
     if (!c) return LBM_EINVAL;
-    if (c->p.compressible)
-        return fail(c, LBM_ESTATE, "the adjoint covers the incompressible form only");
+    if (adjoint_ok(c) != LBM_OK) return LBM_ESTATE;
     if (!u_init || !lam0 || !grad_u) return fail(c, LBM_EINVAL, "u_init, lam0, grad_u must be set");
     hipError_t e = launch_init_vjp(c->g, c->p.stencil, c->p.adjoint_dtype, c->p.equilibrium,
                                    u_init, lam0, grad_u, c->stream);

@@ -40,3 +40,18 @@
 #define LBM_DISPATCH_NT(BODY)                             \
     if (nt) { constexpr bool NT = true; BODY; }           \
     else { constexpr bool NT = false; BODY; }
+
+// Boundary handling of the two-grid stream-collide kernel (kGen*).
+#define LBM_DISPATCH_GEN3(gen, BODY)                                         \
+    if (gen == kGenOpen) { constexpr int GEN = kGenOpen; BODY; }             \
+    else if (gen == kGenWalls) { constexpr int GEN = kGenWalls; BODY; }      \
+    else { constexpr int GEN = kGenPeriodic; BODY; }
+
+// Collision operator of the stream-collide kernels (kCo*); MRT and KBC exist
+// for D3Q19 only.
+#define LBM_DISPATCH_CO(BODY)                                               \
+    if constexpr (QN == 19) {                                               \
+        if (co == kCoMrt) { constexpr int CO = kCoMrt; BODY; }              \
+        else if (co == kCoKbc) { constexpr int CO = kCoKbc; BODY; }         \
+        else { constexpr int CO = kCoPair; BODY; }                          \
+    } else { constexpr int CO = kCoPair; BODY; }

@@ -1,5 +1,6 @@
-// Forward kernels: initial state, fused stream-collide (two-grid pull and AA
-// in-place), canonical read-out / write-in, moments and reductions.
+// Forward kernels around the stream-collide update (which lives in
+// step_tg.hip and step_aa.hip): initial state, link words, canonical read-out
+// / write-in, moments and reductions.
 //
 // Update: eq. lb_srt_with_forces (Sec. 2.3) with the Buick forcing term
 // F_q = 3 w_q c_q.a, the force-shifted velocity of eq. macroscopic_vel_shift,
@@ -121,14 +122,6 @@ __global__ __launch_bounds__(kBlock) void k_init_maxdev(Geom g, int compressible
     block_reduce<1, true>(m, partials + blockIdx.x);
 }
 
-// Memory hints of the stream-collide kernels for direction q (x component
-// cx): with NT (the streaming cache policy) as set by LBM_NT_FWD_LOADS and
-// LBM_NT_FWD_STORES, none otherwise.
-template <bool NT>
-__host__ __device__ constexpr bool fwd_load_hint(int cx) { return NT && hint_of(LBM_NT_FWD_LOADS, cx); }
-template <bool NT>
-__host__ __device__ constexpr bool fwd_store_hint(int cx) { return NT && hint_of(LBM_NT_FWD_STORES, cx); }
-
 // Link words (Geom::links) of a lattice with walls or solid cells, from the
 // periodic flags and the caller's mask (nullptr: all fluid).  Built once.
 template <int QN>
@@ -148,188 +141,12 @@ __global__ __launch_bounds__(kBlock) void k_links(Geom g, const uint8_t *__restr
     links[idx] = w;
 }
 
-// ---------------------------------------------------------------------------
-// Two-grid pull step: dst[q][x] = f*_q(x) from src.
-// ---------------------------------------------------------------------------
-template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR, bool NT>
-__global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<DT>::R> P,
-                                                    const typename Store<DT>::T *__restrict__ src,
-                                                    typename Store<DT>::T *__restrict__ dst,
-                                                    uint32_t key) {
-    using S = Store<DT>;
-    using R = typename S::R;
-    using T = typename S::T;
-    R d[QN];
-    if constexpr (!GEN) {
-        // periodic, no mask: planar launch (blockIdx.y = z)
-        const uint32_t z = blockIdx.y, p = blockIdx.x * kBlock + threadIdx.x;
-        if (p >= g.nxy) return;
-        const PlaneHood h = make_plane_hood(p, z, g);
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            const T *base = src + ((int64_t)h.zp[1 - kC[q].z] * QN + q) * g.qstride;
-            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(
-                at_bytes(base, plane_off<T>(h, q, -1)), 0, (R)wq(QN, q), P.inv_s);
-        });
-        collide<R, EQ, QN, MRT>(d, P);
-        SrBits rb{SR ? mix32((z * g.nxy + p) ^ key) : 0u};
-        const uint32_t off = p * (uint32_t)sizeof(T);
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            constexpr bool H = fwd_store_hint<NT>(0);   // aligned stores
-            T *o = at_bytes(dst + ((int64_t)z * QN + q) * g.qstride, off);
-            if constexpr (SR)
-                store_sr<DT, H>(o, 0, d[q], P.s, rb.next(q));
-            else
-                S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
-        });
-    } else {
-        const uint32_t idx = cell_index();
-        if (idx >= g.ncells) return;
-        const Hood h = make_hood_links<QN>(idx, g);
-        if (link_solid(h.link)) return;
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            bool fl;
-            int64_t pos;
-            hood_cell<GEN>(h, g, q, -1, fl, pos);
-            const T *p = src + (fl ? q : opp(q)) * g.qstride;
-            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
-                                                                 P.inv_s);
-        });
-        collide<R, EQ, QN, MRT>(d, P);
-        SrBits rb{SR ? mix32(idx ^ key) : 0u};
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            constexpr bool H = fwd_store_hint<NT>(0);   // aligned stores
-            if constexpr (SR)
-                store_sr<DT, H>(dst + q * g.qstride, h.pos, d[q], P.s, rb.next(q));
-            else
-                S::template store<H>(dst + q * g.qstride, h.pos, d[q], (R)wq(QN, q), P.s);
-        });
-    }
-}
-
-// ---------------------------------------------------------------------------
-// AA pattern, one buffer updated in place.
-//   neighbour step: g_q(x) = A[qbar][x - c_q] (A[q][x] if x - c_q is not
-//                   fluid); f*_q(x) -> A[q][x + c_q] (A[qbar][x] if x + c_q
-//                   is not fluid).
-//   local step:     g_q(x) = A[q][x];  f*_q(x) -> A[qbar][x].
-// Every slot a cell reads is written by the same cell, so the in-place
-// update is race-free.
-// ---------------------------------------------------------------------------
-template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR, bool NT>
-__global__ __launch_bounds__(kBlock) void k_step_aa_nb(Geom g, Coll<typename Store<DT>::R> P,
-                                                       typename Store<DT>::T *A, uint32_t key) {
-    using S = Store<DT>;
-    using R = typename S::R;
-    using T = typename S::T;
-    R d[QN];
-    if constexpr (!GEN) {
-        // periodic, no mask: planar launch (blockIdx.y = z)
-        const uint32_t z = blockIdx.y, p = blockIdx.x * kBlock + threadIdx.x;
-        if (p >= g.nxy) return;
-        const PlaneHood h = make_plane_hood(p, z, g);
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            const T *base = A + ((int64_t)h.zp[1 - kC[q].z] * QN + opp(q)) * g.qstride;
-            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(
-                at_bytes(base, plane_off<T>(h, q, -1)), 0, (R)wq(QN, q), P.inv_s);
-        });
-        collide<R, EQ, QN, MRT>(d, P);
-        SrBits rb{SR ? mix32((z * g.nxy + p) ^ key) : 0u};
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            constexpr bool H = fwd_store_hint<NT>(kC[q].x);
-            T *o = at_bytes(A + ((int64_t)h.zp[1 + kC[q].z] * QN + q) * g.qstride,
-                            plane_off<T>(h, q, +1));
-            if constexpr (SR)
-                store_sr<DT, H>(o, 0, d[q], P.s, rb.next(q));
-            else
-                S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
-        });
-    } else {
-        const uint32_t idx = cell_index();
-        if (idx >= g.ncells) return;
-        const Hood h = make_hood_links<QN>(idx, g);
-        if (link_solid(h.link)) return;
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            bool fl;
-            int64_t pos;
-            hood_cell<GEN>(h, g, q, -1, fl, pos);
-            const typename S::T *p = A + (fl ? opp(q) : q) * g.qstride;
-            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
-                                                                 P.inv_s);
-        });
-        collide<R, EQ, QN, MRT>(d, P);
-        SrBits rb{SR ? mix32(idx ^ key) : 0u};
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            constexpr bool H = fwd_store_hint<NT>(kC[q].x);
-            bool fl;
-            int64_t pos;
-            hood_cell<GEN>(h, g, q, +1, fl, pos);
-            typename S::T *p = A + (fl ? q : opp(q)) * g.qstride;
-            if constexpr (SR)
-                store_sr<DT, H>(p, fl ? pos : h.pos, d[q], P.s, rb.next(q));
-            else
-                S::template store<H>(p, fl ? pos : h.pos, d[q], (R)wq(QN, q), P.s);
-        });
-    }
-}
-
-template <int QN, int DT, int EQ, bool GEN, bool MRT, bool SR, bool NT>
-__global__ __launch_bounds__(kBlock) void k_step_aa_loc(Geom g, Coll<typename Store<DT>::R> P,
-                                                        typename Store<DT>::T *A, uint32_t key) {
-    using S = Store<DT>;
-    using R = typename S::R;
-    using T = typename S::T;
-    R d[QN];
-    if constexpr (!GEN) {
-        // periodic, no mask: planar launch (blockIdx.y = z)
-        const uint32_t z = blockIdx.y, p = blockIdx.x * kBlock + threadIdx.x;
-        if (p >= g.nxy) return;
-        const uint32_t off = p * (uint32_t)sizeof(T);
-        T *plane = A + (int64_t)z * QN * g.qstride;
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            d[q] = S::template load<fwd_load_hint<NT>(0)>(at_bytes(plane + q * g.qstride, off), 0,
-                                                          (R)wq(QN, q), P.inv_s);
-        });
-        collide<R, EQ, QN, MRT>(d, P);
-        SrBits rb{SR ? mix32((z * g.nxy + p) ^ key) : 0u};
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            constexpr bool H = fwd_store_hint<NT>(0);
-            T *o = at_bytes(plane + opp(q) * g.qstride, off);
-            if constexpr (SR)
-                store_sr<DT, H>(o, 0, d[q], P.s, rb.next(q));
-            else
-                S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
-        });
-    } else {
-        const uint32_t idx = cell_index();
-        if (idx >= g.ncells) return;
-        if (is_solid(g, idx)) return;
-        const int64_t pos = cell_pos(idx, g);
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            d[q] = S::template load<fwd_load_hint<NT>(0)>(A + q * g.qstride, pos, (R)wq(QN, q),
-                                                          P.inv_s);
-        });
-        collide<R, EQ, QN, MRT>(d, P);
-        SrBits rb{SR ? mix32(idx ^ key) : 0u};
-        static_for<QN>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            constexpr bool H = fwd_store_hint<NT>(0);
-            if constexpr (SR)
-                store_sr<DT, H>(A + opp(q) * g.qstride, pos, d[q], P.s, rb.next(q));
-            else
-                S::template store<H>(A + opp(q) * g.qstride, pos, d[q], (R)wq(QN, q), P.s);
-        });
-    }
+// Whether each 256-cell block holds a fluid cell (for the active list).
+__global__ __launch_bounds__(kBlock) void k_block_fluid(Geom g, uint32_t *__restrict__ flags) {
+    const uint32_t idx = cell_index();
+    const int fluid = idx < g.ncells && !link_solid(g.links[idx]);
+    const int any = __syncthreads_or(fluid);
+    if (threadIdx.x == 0) flags[blockIdx.x] = any ? 1u : 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -523,23 +340,6 @@ __global__ __launch_bounds__(kBlock) void k_copy(const u32x4 *__restrict__ src,
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-
-
-// Stochastic rounding exists for the 16-bit formats only.
-#define LBM_DISPATCH_SR(BODY)                                                       \
-    if constexpr (DT == LBM_F16_SHIFTED || DT == LBM_BF16_SHIFTED) {                \
-        if (sr) { constexpr bool SR = true; BODY; }                                 \
-        else { constexpr bool SR = false; BODY; }                                   \
-    } else { constexpr bool SR = false; BODY; }
-
-// Dynamic LDS reserved per stream-collide block (residency cap).
-static constexpr unsigned step_lds_bytes(int qn, int dtype, bool gen) {
-    return qn == 27 ? LBM_STEP27_LDS_BYTES
-           : dtype == LBM_F32 || dtype == LBM_F32_SHIFTED ? LBM_STEP_LDS_BYTES_4B
-           : gen && dtype != LBM_F64 ? LBM_STEP_LDS_BYTES_GEN16
-                                     : LBM_STEP_LDS_BYTES;
-}
-
 hipError_t launch_init(const Geom &g, int qn, int dtype, int eq, int compressible, Layout layout,
                        const double *rho, const double *u, void *A, void *B, double s,
                        hipStream_t st) {
@@ -574,37 +374,8 @@ hipError_t launch_links(const Geom &g, int qn, const uint8_t *solid, uint32_t *l
     return hipGetLastError();
 }
 
-hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
-                          bool sr, bool nt, uint32_t key, const CollBoth &P, const void *src,
-                          void *dst, hipStream_t st) {
-    // GEN = false runs the planar launch; lattices it cannot address take the
-    // general kernel, which is exact for periodic lattices without a mask too.
-    gen = gen || !planar_ok(g);
-    const dim3 grid = gen ? dim3(cell_blocks(g)) : plane_grid(g), block(kBlock);
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(
-        LBM_DISPATCH_SR(LBM_DISPATCH_NT({
-        using T = typename Store<DT>::T;
-        hipLaunchKernelGGL((k_step_tg<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
-                           step_lds_bytes(QN, DT, GEN), st, g, pick<DT>(P), (const T *)src, (T *)dst, key);
-    }))))));
-    return hipGetLastError();
-}
-
-hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
-                          bool sr, bool nt, uint32_t key, bool neighbor, const CollBoth &P,
-                          void *A, hipStream_t st) {
-    gen = gen || !planar_ok(g);   // as in launch_step_tg
-    const dim3 grid = gen ? dim3(cell_blocks(g)) : plane_grid(g), block(kBlock);
-    LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN(gen, LBM_DISPATCH_MRT(
-        LBM_DISPATCH_SR(LBM_DISPATCH_NT({
-        using T = typename Store<DT>::T;
-        if (neighbor)
-            hipLaunchKernelGGL((k_step_aa_nb<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
-                               step_lds_bytes(QN, DT, GEN), st, g, pick<DT>(P), (T *)A, key);
-        else
-            hipLaunchKernelGGL((k_step_aa_loc<QN, DT, EQ, GEN, MRT, SR, NT>), grid, block,
-                               step_lds_bytes(QN, DT, GEN), st, g, pick<DT>(P), (T *)A, key);
-    }))))));
+hipError_t launch_block_fluid(const Geom &g, uint32_t *flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_fluid, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, flags);
     return hipGetLastError();
 }
 

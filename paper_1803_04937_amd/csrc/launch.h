@@ -54,10 +54,14 @@ hipError_t launch_init_maxdev(const Geom &g, int qn, int eq, int compressible, c
 // Link words of the lattice (Geom::links) from the walls and the mask.
 hipError_t launch_links(const Geom &g, int qn, const uint8_t *solid, uint32_t *links,
                         hipStream_t st);
-hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
+// flags[b] = 1 when 256-cell block b holds a fluid cell (g.links set), else 0.
+hipError_t launch_block_fluid(const Geom &g, uint32_t *flags, hipStream_t st);
+// co: collision operator (kCo*); gen: boundary handling (kGen*); the AA
+// steps take no open faces.
+hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, int co, int gen,
                           bool sr, bool nt, uint32_t key, const CollBoth &P, const void *src,
                           void *dst, hipStream_t st);
-hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, bool mrt, bool gen,
+hipError_t launch_step_aa(const Geom &g, int qn, int dtype, int eq, int co, bool gen,
                           bool sr, bool nt, uint32_t key, bool neighbor, const CollBoth &P,
                           void *A, hipStream_t st);
 hipError_t launch_get(const Geom &g, int qn, int dtype, Layout layout, double inv_s, const void *A,
@@ -90,6 +94,8 @@ hipError_t launch_finalize(const Scratch &sc, uint32_t nblocks, int nvals, int o
 hipError_t launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t st);
 
 inline uint32_t cell_blocks(const Geom &g) { return (g.ncells + kBlock - 1) / kBlock; }
+// Workgroups of a launch over the active list (see Geom::active).
+inline uint32_t gen_blocks(const Geom &g) { return g.active ? g.nactive : cell_blocks(g); }
 // Planar launch (blocks of one z-plane each): possible when the planes fit
 // the grid's second dimension and a plane's FP64 bytes fit 32-bit offsets.
 inline bool planar_ok(const Geom &g) {

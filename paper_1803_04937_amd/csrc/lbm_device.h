@@ -411,8 +411,34 @@ struct Geom {
     // neighbour, which would put a dependent mask load in front of every
     // pull and made masked lattices 2.4-4.5 times slower.
     const uint32_t *links;
+    // Open x faces (kernels with GEN == kGenOpen): inflow velocity at the
+    // inlet cells, device double [3][nz][ny] (caller-owned).
+    const double *inlet;
+    // Lattices with a mask: the 256-cell blocks that hold at least one fluid
+    // cell, ascending (caller-owned, after the link words), and their count;
+    // nullptr when every block does.  The stream-collide kernels with walls
+    // or a mask, and the adjoint when it leaves solid cells unwritten, run one
+    // workgroup per listed block only.
+    const uint32_t *active;
+    uint32_t nactive;
 };
+
+// Cell block of this workgroup in a launch over the active list (or over
+// every block when there is none).
+__device__ __forceinline__ uint32_t gen_block(const Geom &g) {
+    return g.active ? g.active[blockIdx.x] : blockIdx.x;
+}
 constexpr int kSolidBit = 31;
+
+// Boundary handling of the stream-collide kernels (template parameter GEN):
+// fully periodic without a mask (planar launch), walls and / or a mask, and
+// walls / mask with an open inlet face at x = -1/2 and outlet face at
+// x = nx - 1/2.
+constexpr int kGenPeriodic = 0, kGenWalls = 1, kGenOpen = 2;
+
+// Collision operators of the stream-collide kernels (template parameter CO):
+// SRT / TRT in pair form, MRT (Sec. 3.2), KBC (Sec. 3.3).
+constexpr int kCoPair = 0, kCoMrt = 1, kCoKbc = 2;
 constexpr uint32_t kAllLinks = ~(1u << kSolidBit);   // fluid, every neighbour fluid
 
 __device__ __forceinline__ bool link_solid(uint32_t w) { return (w >> kSolidBit) & 1u; }
@@ -563,6 +589,10 @@ struct Coll {
     R ke[100];
     R ko[81];
     R pe2[100];     // d K_e / d omega (MRT adjoint)
+    // KBC (D3Q19), with beta = omega / 2: 1/beta, 2 - 1/beta and the upper
+    // bound 2 of the stabiliser gamma
+    R kbc_ib, kbc_c, kbc_hi;
+    R drho_out;     // open faces: outlet density - 1
 };
 
 // Moments of shifted PDFs: drho = sum d, j = sum c d.
@@ -715,8 +745,61 @@ struct Poly {
 // (Sec. 3.2, C = -M^-1 S (M f - m_eq)) the even and odd non-equilibrium
 // vectors are relaxed with the matrices K_e, K_o instead of the scalars
 // omega, omega_minus; the force enters as (I - K_o/2) F.
-template <typename R, int EQ, int QN = 19, bool MRT = false>
+template <typename R>
+__device__ __forceinline__ R recip(R x) {
+    if constexpr (sizeof(R) == 4)
+        return __builtin_amdgcn_rcpf(x);   // 1 ulp; the stabiliser needs no more
+    else
+        return R(1) / x;
+}
+
+// KBC collision (Sec. 3.3) of one cell in pair coordinates, from the
+// non-equilibrium parts ne0 (rest), ne[p] (half pair sums), no[p] (half pair
+// differences) of g - f^eq.  The populations split by the 19 kept monomial
+// moments of Sec. 3.2 into a kinematic part (orders 0, 1), a shear part s
+// (orders 2, 3; the KBC-N4 choice) and a higher-order part h (order 4):
+//   f* = g - omega (g - f^eq) - (gamma beta - omega) dh + (1 - omega/2) F,
+// beta = omega / 2, which relaxes s at omega and h at gamma beta.  The order-4
+// moments x^2y^2, x^2z^2, y^2z^2 of g - f^eq are the sums over the xy, xz,
+// yz edge pairs; their dual basis vectors of the 19 moments are 1 at rest,
+// -1/2 on the two axes and 1/4 on the four edges of the plane, so dh is even.
+// gamma minimises the entropic norm sum (f* - f^eq)^2 / f^eq over
+// 0 <= gamma <= 2 (the higher-order part relaxes at most as fast as the shear
+// part; rates closer to 2 let rounding noise grow in moments that dh barely
+// contains): gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh> clamped to
+// [0, 2], 2 when <dh|dh> = 0, with ds = g - f^eq - dk - dh
+// and dk the kinematic part (momentum -a/2: -a_i/4 on the axis pair i's odd
+// part).  feq0, feqp, feqm: f^eq of the rest, q and qbar directions.
+template <typename R>
+__device__ __forceinline__ R kbc_kappa(R ne0, const R (&ne)[9], const R (&no)[9], R feq0,
+                                       const R (&feqp)[9], const R (&feqm)[9],
+                                       const Coll<R> &P, R (&hp)[9], R &h0) {
+    const R Hxy = R(2) * (ne[3] + ne[4]), Hxz = R(2) * (ne[5] + ne[6]),
+            Hyz = R(2) * (ne[7] + ne[8]);
+    h0 = (Hxy + Hxz) + Hyz;
+    hp[0] = R(-0.5) * (Hxy + Hxz);
+    hp[1] = R(-0.5) * (Hxy + Hyz);
+    hp[2] = R(-0.5) * (Hxz + Hyz);
+    hp[3] = hp[4] = R(0.25) * Hxy;
+    hp[5] = hp[6] = R(0.25) * Hxz;
+    hp[7] = hp[8] = R(0.25) * Hyz;
+    R sh = (ne0 - h0) * h0 * recip(feq0), hh = h0 * h0 * recip(feq0);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const R se = ne[p] - hp[p];
+        const R so = p < 3 ? no[p] + R(0.5) * P.ah[p] : no[p];
+        const R ip = recip(feqp[p]), im = recip(feqm[p]);
+        sh += hp[p] * ((se + so) * ip + (se - so) * im);
+        hh += hp[p] * hp[p] * (ip + im);
+    }
+    R gamma = R(2);
+    if (hh != R(0)) gamma = fmin(fmax(P.kbc_ib - P.kbc_c * (sh / hh), R(0)), P.kbc_hi);
+    return P.wp * (R(0.5) * gamma - R(1));   // gamma beta - omega
+}
+
+template <typename R, int EQ, int QN = 19, int CO = kCoPair>
 __device__ __forceinline__ void collide(R (&d)[QN], const Coll<R> &P) {
+    constexpr bool MRT = CO == kCoMrt;
     constexpr int NP = (QN - 1) / 2;
     R drho, jx, jy, jz;
     moments<R, QN>(d, drho, jx, jy, jz);
@@ -768,6 +851,32 @@ __device__ __forceinline__ void collide(R (&d)[QN], const Coll<R> &P) {
             const int q = 2 * p + 1;
             d[q] = d[q] - te[p + 1] - to[p];
             d[q + 1] = d[q + 1] - te[p + 1] + to[p];
+        }
+        return;
+    }
+    if constexpr (CO == kCoKbc && QN == 19) {
+        R ne[9], no[9], fp[9], fm[9];
+        const R ne0 = d[0] - w0 * (drho + rho0 * E0);
+        const R feq0 = w0 * ((R(1) + drho) + rho0 * E0);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const int q = 2 * p + 1;
+            const R w = R(wq(QN, q));
+            ne[p] = R(0.5) * (d[q] + d[q + 1]) - w * (drho + rho0 * E[p]);
+            no[p] = R(0.5) * (d[q] - d[q + 1]) - w * rho0 * O[p];
+            fp[p] = w * ((R(1) + drho) + rho0 * (E[p] + O[p]));
+            fm[p] = w * ((R(1) + drho) + rho0 * (E[p] - O[p]));
+        }
+        R hp[9], h0;
+        const R kap = kbc_kappa<R>(ne0, ne, no, feq0, fp, fm, P, hp, h0);
+        d[0] = d[0] - P.wp * ne0 - kap * h0;
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const int q = 2 * p + 1;
+            const R tp = P.wp * ne[p] + kap * hp[p];
+            const R tm = P.wp * no[p] - P.fpair[p];
+            d[q] = d[q] - tp - tm;
+            d[q + 1] = d[q + 1] - tp + tm;
         }
         return;
     }

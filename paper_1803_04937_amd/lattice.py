@@ -12,7 +12,8 @@ from .capi import LBMError
 
 EQUILIBRIA = {"standard": capi.LBM_EQ_STANDARD, "improved": capi.LBM_EQ_IMPROVED,
               "improved3": capi.LBM_EQ_IMPROVED3}
-COLLISIONS = {"srt": capi.LBM_SRT, "trt": capi.LBM_TRT, "mrt": capi.LBM_MRT}
+COLLISIONS = {"srt": capi.LBM_SRT, "trt": capi.LBM_TRT, "mrt": capi.LBM_MRT,
+              "kbc": capi.LBM_KBC}
 DTYPES = {"f64": capi.LBM_F64, "f32": capi.LBM_F32, "f32s": capi.LBM_F32_SHIFTED,
           "f16s": capi.LBM_F16_SHIFTED, "bf16s": capi.LBM_BF16_SHIFTED}
 PATTERNS = {"two_grid": capi.LBM_TWO_GRID, "aa": capi.LBM_AA}
@@ -44,13 +45,16 @@ class Lattice:
     (nz, ny, nx); solid: optional mask (nz, ny, nx), nonzero = solid.
     adjoint_solid: "copy" (adjoint_step copies lambda through solid cells)
     or "skip" (leaves it unwritten there).
+    inlet: with open_x, the inflow velocity (3, nz, ny) of the inlet cells
+    (x = 0); rho_out: the outlet density.
     """
 
     def __init__(self, nx, ny, nz, *, u, rho=None, solid=None, periodic=(1, 1, 1),
                  equilibrium="improved", collision="srt", dtype="f32", pattern="two_grid",
                  compressible=False, omega=1.0, trt_magic=3.0 / 16.0, accel=(0.0, 0.0, 0.0),
                  scale=0.0, stencil=19, mrt_omega3=1.0, mrt_omega4=1.0, rounding="nearest",
-                 seed=0, cache_policy="auto", adjoint_solid="copy", device=None, stream=None):
+                 seed=0, cache_policy="auto", adjoint_solid="copy", open_x=False, inlet=None,
+                 rho_out=1.0, device=None, stream=None):
         self.device = require_gpu(device)
         self.params = capi.make_params(
             nx, ny, nz, periodic=periodic, equilibrium=_code(EQUILIBRIA, equilibrium),
@@ -60,7 +64,8 @@ class Lattice:
             mrt_omega3=mrt_omega3, mrt_omega4=mrt_omega4,
             rounding=_code(ROUNDINGS, rounding), seed=seed,
             cache_policy=_code(CACHE_POLICIES, cache_policy),
-            adjoint_solid=_code(ADJOINT_SOLID, adjoint_solid))
+            adjoint_solid=_code(ADJOINT_SOLID, adjoint_solid), open_x=int(bool(open_x)),
+            rho_out=rho_out)
         rc, why = capi.lbm_validate(self.params)
         if rc != capi.LBM_OK:
             raise LBMError(rc, why)
@@ -72,9 +77,14 @@ class Lattice:
         self.adjoint_dtype = ADJ_TORCH[self.params.adjoint_dtype]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.solid = None
+        self.links = None
         if solid is not None:
             self.solid = torch.as_tensor(solid).to(self.device, torch.uint8).contiguous()
             assert self.solid.shape == self.shape
+            # uint32 link words (one per cell) and the list of blocks with a
+            # fluid cell, written by lbm_init (held as int32)
+            nbytes = capi.lbm_links_bytes(self.params)
+            self.links = torch.empty(nbytes // 4, dtype=torch.int32, device=self.device)
         u = torch.as_tensor(u).to(self.device, torch.float64).contiguous()
         assert u.shape == (3,) + self.shape, u.shape
         if rho is not None:
@@ -84,9 +94,13 @@ class Lattice:
         if self.params.pattern == capi.LBM_TWO_GRID:
             self.buffers.append(self.new_state())
         self._ctx = None
-        self._ctx = capi.lbm_init(self.params, self.solid, self.buffers[0],
+        self._ctx = capi.lbm_init(self.params, self.solid, self.links, self.buffers[0],
                                   self.buffers[1] if len(self.buffers) > 1 else None,
                                   self.stream.cuda_stream, rho, u)
+        self.inlet = None
+        if open_x:
+            self.set_inlet(torch.zeros((3, self.shape[0], self.shape[1])) if inlet is None
+                           else inlet)
 
     # -- buffers -------------------------------------------------------------
     def new_state(self) -> torch.Tensor:
@@ -175,6 +189,14 @@ class Lattice:
 
     def set_rates(self, omega: float, accel=None) -> None:
         capi.lbm_set_rates(self.ctx, omega, accel)
+
+    def set_inlet(self, u_in) -> None:
+        """Inflow velocity (3, nz, ny) of the inlet cells of an open lattice;
+        kept on the device as long as the lattice uses it."""
+        u_in = torch.as_tensor(u_in).to(self.device, torch.float64).contiguous()
+        assert u_in.shape == (3, self.shape[0], self.shape[1]), u_in.shape
+        capi.lbm_set_inlet(self.ctx, u_in)
+        self.inlet = u_in
 
     # -- adjoint -------------------------------------------------------------
     def adjoint_step(self, state_t, lam_next, lam_prev, grad=None) -> None:

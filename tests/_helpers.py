@@ -142,3 +142,25 @@ def push_targets(cfg, cells):
         arr[:, r] = np.where(fluid, r, opp[r])
         tgt[:, r] = np.where(fluid, src, cells)
     return arr, tgt
+
+
+# Per-element bound of an adjoint field (lambda) against the oracle:
+# |got - want| <= tol * max(|want|, floor * max|want|).  The floor covers
+# values that are small because their terms cancel: their rounding error
+# scales with the terms (about max|lambda|), not with the value.
+ADJ_TOL = {"f64": (1e-12, 1e-2), "f32": (2e-6, 0.25)}
+
+
+def assert_adjoint_parity(got, want, dtype, what=""):
+    tol, floor = ADJ_TOL["f64" if dtype == "f64" else "f32"]
+    m = np.abs(want).max()
+    bound = tol * np.maximum(np.abs(want), floor * m)
+    err = np.abs(got - want)
+    worst = (err / bound).max()
+    # error profile for the record: worst error relative to the largest value,
+    # and among the values below a tenth of it
+    small = np.abs(want) < 0.1 * m
+    prof = (err.max() / m, (err[small].max() / m) if small.any() else 0.0)
+    print(f"adjoint parity {what} {dtype}: worst {worst:.3f} x bound, "
+          f"max err / max {prof[0]:.2e}, small-value err / max {prof[1]:.2e}")
+    assert worst <= 1.0, f"{what}: {worst:.2f} x bound"

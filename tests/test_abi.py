@@ -88,7 +88,13 @@ BAD = [
     (dict(collision=2, stencil=27), "MRT"),
     (dict(collision=2, mrt_omega3=0.0), "mrt_omega3"),
     (dict(collision=2, mrt_omega4=2.5), "mrt_omega4"),
-    (dict(collision=3), "collision"),
+    (dict(collision=4), "collision"),
+    (dict(collision=3, stencil=27), "KBC"),
+    (dict(open_x=2), "open_x"),
+    (dict(open_x=1), "periodic[0]"),
+    (dict(open_x=1, periodic=(0, 1, 1), pattern=1), "two-grid"),
+    (dict(open_x=1, periodic=(0, 1, 1), compressible=1), "incompressible"),
+    (dict(open_x=1, periodic=(0, 1, 1), rho_out=0.0), "rho_out"),
     (dict(rounding=2), "rounding"),
     (dict(cache_policy=3), "cache_policy"),
     (dict(adjoint_solid=2), "adjoint_solid"),
@@ -105,24 +111,54 @@ def test_invalid_parameters_are_rejected(capi, kw, why):
     assert why in msg
     # lbm_init refuses the same parameters before any GPU call
     with pytest.raises(capi.LBMError) as e:
-        capi.lbm_init(p, None, 1 << 20, 2 << 20, None, None, 3 << 20)
+        capi.lbm_init(p, None, None, 1 << 20, 2 << 20, None, None, 3 << 20)
     assert e.value.status == capi.LBM_EINVAL
     assert why in str(e.value)
 
 
 def test_init_argument_checks(capi):
     p = capi.make_params(8, 8, 8)
-    for args, why in [((None, 0, 0, None, None, 1), "pdf0"),
-                      ((None, 16, None, None, None, 1), "second"),
-                      ((None, 16, 16, None, None, 1), "second"),
-                      ((None, 16, 32, None, None, None), "u_init")]:
+    for args, why in [((None, None, 0, 0, None, None, 1), "pdf0"),
+                      ((None, None, 16, None, None, None, 1), "second"),
+                      ((None, None, 16, 16, None, None, 1), "second"),
+                      ((None, None, 16, 32, None, None, None), "u_init"),
+                      ((64, None, 16, 32, None, None, 1), "link-word buffer")]:
         with pytest.raises(capi.LBMError) as e:
             capi.lbm_init(p, *args)
         assert why in str(e.value)
     paa = capi.make_params(8, 8, 8, pattern=capi.LBM_AA)
     with pytest.raises(capi.LBMError) as e:
-        capi.lbm_init(paa, None, 16, 32, None, None, 1)
+        capi.lbm_init(paa, None, None, 16, 32, None, None, 1)
     assert "one buffer" in str(e.value)
+
+
+def test_links_bytes(capi):
+    p = capi.make_params(37, 19, 15)
+    n = 37 * 19 * 15
+    assert capi.lbm_links_bytes(p) == (n + (n + 255) // 256) * 4
+
+
+def test_choose_scale_rule(capi):
+    """Scale of the 16-bit formats: 2^floor(log2(1024 / maxdev)) clamped to
+    [2^-10, 2^14], 2^14 at rest, monotone in maxdev, 1 for other dtypes; at
+    the cap, s (f - w) stays inside FP16's normal range for |f - w| in
+    [2^-28, 4)."""
+    f16, bf16 = capi.LBM_F16_SHIFTED, capi.LBM_BF16_SHIFTED
+    assert capi.lbm_choose_scale(f16, 0.0) == 2.0 ** 14
+    assert capi.lbm_choose_scale(f16, 1e-6) == 2.0 ** 14     # near rest: capped
+    assert capi.lbm_choose_scale(f16, 1e-30) == 2.0 ** 14
+    assert capi.lbm_choose_scale(f16, 0.1) == 2.0 ** 13       # 1024 / 0.1 = 10240
+    assert capi.lbm_choose_scale(f16, 1.0) == 2.0 ** 10
+    assert capi.lbm_choose_scale(f16, 1e6) == 2.0 ** -10
+    assert capi.lbm_choose_scale(bf16, 0.05) == 2.0 ** 14
+    assert capi.lbm_choose_scale(capi.LBM_F32, 0.05) == 1.0
+    devs = np.logspace(-12, 3, 400)
+    s = [capi.lbm_choose_scale(f16, d) for d in devs]
+    assert all(a >= b for a, b in zip(s, s[1:]))
+    assert 4.0 * 2.0 ** 14 <= 65504 + 2.0 ** 14 and 2.0 ** -28 * 2.0 ** 14 == 2.0 ** -14
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(capi.LBMError):
+            capi.lbm_choose_scale(f16, bad)
 
 
 def test_valid_parameters_pass(capi):

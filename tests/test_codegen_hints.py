@@ -10,6 +10,8 @@ cache-policy bits of every stream-collide and adjoint instantiation:
   cached forward (NT = 0): none;
   streaming adjoint: every PDF and lambda load and every lambda store;
   cached adjoint: none.
+It also checks that no packed FP32 arithmetic (v_pk_add_f32, v_pk_mul_f32,
+v_pk_fma_f32) appears in any kernel: the build disables the feature.
 """
 import os
 import re
@@ -25,10 +27,10 @@ KERNEL = re.compile(r'^(_ZN3lbm\d+(k_step_tg|k_step_aa_nb|k_step_aa_loc|k_adjoin
 
 @pytest.fixture(scope="module")
 def assembly(tmp_path_factory):
-    """gfx950 assembly of both kernel files, compiled concurrently."""
+    """gfx950 assembly of every kernel file, compiled concurrently."""
     d = tmp_path_factory.mktemp("asm")
     procs = {}
-    for src in ("forward.hip", "adjoint.hip"):
+    for src in B.SOURCES:
         cmd = [B.HIPCC, *B.FLAGS, "--cuda-device-only", "-S", os.path.join(B.CSRC, src), "-o",
                str(d / (src + ".s"))]
         procs[src] = subprocess.Popen(cmd, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
@@ -50,7 +52,7 @@ def _counts(asm):
 
 
 def test_forward_hints(assembly):
-    asm = assembly["forward.hip"]
+    asm = assembly["step_tg.hip"] + assembly["step_aa.hip"]
     seen = 0
     for name, kind, nl, ns, _, _ in _counts(asm):
         qn, nt = re.search(r"ILi(\d+)E.*ELb([01])$", name).groups()
@@ -84,3 +86,9 @@ def test_adjoint_hints(assembly):
             assert nl == n_loads and ns == qn + nxs, (name, nl, n_loads, ns)
         seen += 1
     assert seen > 100, seen
+
+
+def test_no_packed_fp32(assembly):
+    for src, asm in assembly.items():
+        hits = re.findall(r"v_pk_(?:add|mul|fma)_f32", asm)
+        assert not hits, (src, len(hits))

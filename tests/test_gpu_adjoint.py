@@ -7,7 +7,7 @@ import torch
 
 import lbm_inputs
 import oracle
-from _helpers import W, case, dev, host, lattice, random_blobs
+from _helpers import W, assert_adjoint_parity, case, dev, host, lattice, random_blobs
 
 pytestmark = pytest.mark.gpu
 
@@ -49,8 +49,7 @@ def test_adjoint_step_matches_oracle(improved, trt, dtype):
     got = host(lat.state_view(lp)).astype(np.float64)
     want, gw = oracle.adjoint_step(cfg, f_stored, lam)
     tol = 1e-12 if dtype == "f64" else 2e-6
-    scale = np.abs(want).max()
-    assert np.abs(got - want).max() <= tol * scale, np.abs(got - want).max() / scale
+    assert_adjoint_parity(got, want, dtype, "adjoint step")
     g = host(grad)
     np.testing.assert_allclose(g, gw, rtol=tol * 10, atol=tol * np.abs(gw).max())
 

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import oracle
-from _helpers import case, dev, host, lattice, random_blobs, weights_for
+from _helpers import assert_adjoint_parity, case, dev, host, lattice, random_blobs, weights_for
 
 pytestmark = pytest.mark.gpu
 
@@ -58,8 +58,7 @@ def test_adjoint_rows_match_oracle_f64(shape, walls, stencil):
                    accel=(2e-4, -1e-4, 1e-4), solid=solid, stencil=stencil,
                    improved=0 if stencil == 27 else 1)
     got, want, g, gw = _step(cfg, kw, "f64", 130 + nx)
-    scale = np.abs(want).max()
-    assert np.abs(got - want).max() <= 1e-12 * scale, np.abs(got - want).max() / scale
+    assert_adjoint_parity(got, want, "f64", f"rows {shape} {walls} Q{stencil}")
     np.testing.assert_allclose(g, gw, rtol=1e-11, atol=1e-12 * np.abs(gw).max())
 
 
@@ -69,6 +68,5 @@ def test_adjoint_rows_fast_path_f32(shape):
     nx, ny, nz = shape
     cfg, kw = case(nx, ny, nz, periodic=(1, 1, 1), trt=True, omega=1.8, improved=1)
     got, want, g, gw = _step(cfg, kw, "f32", 140 + nx)
-    scale = np.abs(want).max()
-    assert np.abs(got - want).max() <= 2e-6 * scale, np.abs(got - want).max() / scale
+    assert_adjoint_parity(got, want, "f32", f"rows {shape} fast path")
     np.testing.assert_allclose(g, gw, rtol=2e-5, atol=2e-6 * np.abs(gw).max())

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from _helpers import case, dev, host, lattice, random_blobs, weights_for
+from _helpers import assert_adjoint_parity, case, dev, host, lattice, random_blobs, weights_for
 
 pytestmark = pytest.mark.gpu
 
@@ -55,8 +55,7 @@ def test_wide_adjoint_step_matches_oracle(name, dtype):
     got = host(lat.state_view(lp)).astype(np.float64)
     want, gw = oracle.adjoint_step(cfg, f_stored, lam)
     tol = 1e-12 if dtype == "f64" else 2e-6
-    scale = np.abs(want).max()
-    assert np.abs(got - want).max() <= tol * scale, np.abs(got - want).max() / scale
+    assert_adjoint_parity(got, want, dtype, name)
     np.testing.assert_allclose(host(grad), gw, rtol=tol * 10, atol=tol * np.abs(gw).max())
     lat.close()
 

@@ -1,0 +1,109 @@
+"""Full-size FP64 GPU runs against reference values made by the FP64 CPU
+oracle (tests/golden/, written by make_oracle_goldens.py, which calls only
+the oracle and the seeded input generators):
+
+* 256^3 random-phase shear waves, omega = 1.95, 1000 steps, D3Q19-S SRT and
+  D3Q19-I TRT (Lambda = 3/16), two-grid and AA: every PDF of ~530 sampled
+  cells within 1e-12 max(|f|, w_q) of the oracle's.
+* The 512 x 128 x 128 duct (x periodic, walls on y and z), D3Q19-I SRT,
+  omega = 1.9, g_x = 1e-6, T = 500: the FP64 GPU objective against the
+  oracle's, and the FP32 checkpointed adjoint gradient (g_x, omega and a
+  seeded direction of the initial velocity) against the oracle's central
+  differences.
+A reference that has not been generated skips its test, with that reason."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+from _helpers import W, dev, host
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _npz(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated (tests/golden/make_oracle_goldens.py)")
+    return np.load(path, allow_pickle=False)
+
+
+@pytest.mark.parametrize("pattern", ["two_grid", "aa"])
+@pytest.mark.parametrize("model", ["S_srt", "I_trt"])
+def test_shear256_fp64_1000_steps(model, pattern):
+    from paper_1803_04937_amd import Lattice
+    z = _npz(f"c2_256_w195_{model}.npz")
+    meta = json.loads(str(z["meta"]))
+    cells, want = z["cells"], z["pdfs"]
+    n = meta["n"]
+    u0 = lbm_inputs.shear_waves((n, n, n), seed=4)
+    lat = Lattice(n, n, n, u=dev(u0), equilibrium=meta["equilibrium"],
+                  collision=meta["collision"], omega=meta["omega"], trt_magic=meta["magic"],
+                  dtype="f64", pattern=pattern)
+    del u0
+    lat.step(meta["steps"])
+    got = host(lat.sample_pdfs(cells))
+    lat.close()
+    bound = 1e-12 * np.maximum(np.abs(want), W[None, :])
+    worst = (np.abs(got - want) / bound).max()
+    print(f"\nshear256 {model} {pattern}: worst {worst:.3f} x the 1e-12 bound, "
+          f"max abs err {np.abs(got - want).max():.2e}")
+    assert worst <= 1.0
+
+
+def _fd_run(nx, ny, nz, T, u0, gx, omega):
+    from paper_1803_04937_amd import Lattice
+    lat = Lattice(nx, ny, nz, u=dev(u0), periodic=(1, 0, 0), equilibrium="improved",
+                  collision="srt", dtype="f64", omega=omega, accel=(gx, 0.0, 0.0))
+    lat.step(T)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    lam = lat.new_adjoint(zero=False)
+    lat.objective(0, lat.state, out, lam)
+    J = out[0].item()
+    lat.close()
+    return J
+
+
+def test_duct_gradient_against_oracle_differences():
+    from paper_1803_04937_amd import RolloutConfig, rollout_objective
+    path = os.path.join(GOLDEN, "c4_duct_fd.json")
+    if not os.path.exists(path):
+        pytest.skip("c4_duct_fd.json not generated (tests/golden/make_oracle_goldens.py)")
+    ref = json.load(open(path))
+    nx, ny, nz, T = ref["nx"], ref["ny"], ref["nz"], ref["steps"]
+    gx, omega, h = ref["gx"], ref["omega"], ref["h"]
+    nu = (1 / omega - 0.5) / 3
+    u0 = lbm_inputs.duct_poiseuille(nx, ny, nz, gx, nu) + lbm_inputs.perturbation(
+        (nz, ny, nx), seed=9, amp=1e-3)
+    v = lbm_inputs.perturbation((nz, ny, nx), seed=10, amp=1.0)
+    # the FP64 GPU objective against the oracle's
+    J64 = _fd_run(nx, ny, nz, T, u0, gx, omega)
+    assert abs(J64 / ref["J"] - 1) < 1e-11, (J64, ref["J"])
+    # the FP32 checkpointed adjoint against the oracle's central differences
+    rc = RolloutConfig(nx, ny, nz, steps=T, periodic=(1, 0, 0), collision="srt", dtype="f32",
+                       objective=0, checkpoint_every=50)
+    u = dev(u0).requires_grad_(True)
+    a = torch.tensor([gx, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    w = torch.tensor(omega, dtype=torch.float64, requires_grad=True)
+    J32 = rollout_objective(u, a, w, rc)
+    J32.backward()
+    g_u = float((host(u.grad) * v).sum())
+    rel = {"J": abs(J32.item() / ref["J"] - 1),
+           "gx": abs(a.grad[0].item() / ref["dJ_dgx"] - 1),
+           "omega": abs(w.grad.item() / ref["dJ_domega"] - 1),
+           "u_dir": abs(g_u / ref["dJ_du_dot_v"] - 1)}
+    print("\nduct FP32 adjoint vs oracle central differences:",
+          json.dumps({"J_oracle": ref["J"], "J64_gpu": J64, "dJ/dgx": [a.grad[0].item(),
+                      ref["dJ_dgx"]], "dJ/domega": [w.grad.item(), ref["dJ_domega"]],
+                      "dJ/du.v": [g_u, ref["dJ_du_dot_v"]], "rel_err": rel}))
+    assert rel["J"] < 2e-4
+    assert rel["gx"] < 1e-3 and rel["omega"] < 1e-3 and rel["u_dir"] < 1e-3
+    # the GPU FP64 central difference in g_x agrees with the oracle's
+    fd = (_fd_run(nx, ny, nz, T, u0, gx * (1 + h), omega)
+          - _fd_run(nx, ny, nz, T, u0, gx * (1 - h), omega)) / (2 * gx * h)
+    assert abs(fd / ref["dJ_dgx"] - 1) < 1e-6, (fd, ref["dJ_dgx"])

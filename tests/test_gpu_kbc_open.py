@@ -1,0 +1,209 @@
+"""GPU parity of the KBC collision (Sec. 3.3) and of the open inlet / outlet
+faces (Sec. 5.2) against the FP64 oracle: several steps in FP64 to 1e-12 per
+PDF, one step from the same stored state in the reduced storage formats,
+the duct invariant of D3Q19-I under KBC, and the pressure-driven channel."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from _helpers import (assert_f64_parity, dev, host, random_blobs, reduced_bound, W)
+
+pytestmark = pytest.mark.gpu
+
+EQ = {0: "standard", 1: "improved", 2: "improved3"}
+
+
+def _lattice(cfg, u, dtype="f64", pattern="two_grid", collision="kbc", inlet=None, **extra):
+    from paper_1803_04937_amd import Lattice
+    kw = dict(periodic=cfg.periodic, equilibrium=EQ[int(cfg.improved)], collision=collision,
+              omega=cfg.omega, trt_magic=cfg.magic, accel=cfg.accel, dtype=dtype,
+              pattern=pattern)
+    if collision == "mrt":
+        kw.update(mrt_omega3=cfg.omega3, mrt_omega4=cfg.omega4)
+    if cfg.solid is not None:
+        kw["solid"] = dev(cfg.solid, torch.uint8)
+    if cfg.open_x:
+        kw.update(open_x=True, rho_out=cfg.rho_out, inlet=dev(inlet))
+    return Lattice(cfg.nx, cfg.ny, cfg.nz, u=dev(u), **kw, **extra)
+
+
+def _noisy(cfg, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-0.05, 0.05, (3,) + cfg.shape)
+    f = oracle.init(cfg, u, rho=1.0 + 0.01 * rng.standard_normal(cfg.shape))
+    f = f + amp * W[:, None, None, None] * rng.standard_normal(f.shape)
+    if cfg.solid is not None:
+        f[:, cfg.solid.astype(bool)] = W[:, None]
+    return u, f
+
+
+SHAPES = [(11, 7, 6, (1, 0, 1), True), (9, 8, 5, (0, 1, 1), False), (16, 4, 3, (1, 1, 1), False)]
+
+
+@pytest.mark.parametrize("improved", [0, 1, 2])
+@pytest.mark.parametrize("pattern", ["two_grid", "aa"])
+@pytest.mark.parametrize("shape", SHAPES, ids=["walls_mask", "xwalls", "periodic"])
+def test_kbc_fp64(improved, pattern, shape):
+    nx, ny, nz, per, mask = shape
+    solid = random_blobs((nz, ny, nx), 3) if mask else None
+    cfg = oracle.Config(nx, ny, nz, periodic=per, improved=improved, kbc=True, omega=1.85,
+                        accel=(2e-4, -1e-4, 5e-5), solid=solid)
+    u, f = _noisy(cfg, 4)
+    lat = _lattice(cfg, u, pattern=pattern)
+    lat.set_pdfs(f)
+    lat.step(4)
+    assert_f64_parity(host(lat.get_pdfs()), oracle.step(cfg, f, 4), f"kbc {pattern}")
+    lat.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f32s", "f16s", "bf16s"])
+def test_kbc_reduced_one_step(dtype):
+    nx, ny, nz = 13, 9, 7
+    solid = random_blobs((nz, ny, nx), 5)
+    cfg = oracle.Config(nx, ny, nz, periodic=(1, 0, 1), improved=1, kbc=True, omega=1.9,
+                        accel=(1e-4, 0, 0), solid=solid)
+    u, _ = _noisy(cfg, 6)
+    lat = _lattice(cfg, u, dtype=dtype)
+    lat.step(3)
+    f_in = host(lat.get_pdfs())
+    lat.step(1)
+    want = oracle.step(cfg, f_in, 1)
+    got = host(lat.get_pdfs())
+    assert np.all(np.abs(got - want) <= reduced_bound(want, dtype, lat.scale))
+    lat.close()
+
+
+@pytest.mark.parametrize("improved", [0, 1])
+def test_kbc_duct_invariant(improved):
+    """D3Q19-I under KBC keeps u_y = u_z = 0 in an x-invariant duct flow;
+    D3Q19-S does not (Sec. 3.3, Sec. 5.1)."""
+    from paper_1803_04937_amd import Lattice
+    D, w, a = 25, 1.0 / (0.5 + 3 * 0.05), 1e-4
+    nu = (1 / w - 0.5) / 3
+    u = lbm_inputs.duct_poiseuille(1, D, D, a, nu)
+    lat = Lattice(1, D, D, u=dev(u), periodic=(1, 0, 0), equilibrium=EQ[improved],
+                  collision="kbc", omega=w, accel=(a, 0, 0), dtype="f64")
+    lat.step(2000)
+    _, v = lat.moments()
+    v = host(v)
+    ratio = np.abs(v[1:]).max() / np.abs(v[0]).max()
+    if improved:
+        assert ratio < 1e-13, ratio
+    else:
+        assert ratio > 1e-6, ratio
+    lat.close()
+
+
+COLLS = [("srt", {}), ("trt", dict(trt=True)), ("mrt", dict(mrt=True, omega3=1.5, omega4=1.1)),
+         ("kbc", dict(kbc=True))]
+
+
+@pytest.mark.parametrize("coll,ckw", COLLS, ids=[c[0] for c in COLLS])
+@pytest.mark.parametrize("improved", [0, 1, 2])
+@pytest.mark.parametrize("stencil", [19, 27])
+def test_open_faces_fp64(coll, ckw, improved, stencil):
+    if stencil == 27 and coll in ("mrt", "kbc"):
+        pytest.skip("MRT and KBC are D3Q19 only")
+    if stencil == 27 and improved:
+        pytest.skip("D3Q27 has one equilibrium")
+    nx, ny, nz = 12, 7, 5
+    solid = random_blobs((nz, ny, nx), 7)
+    solid[:, :, 0] = 0
+    rng = np.random.default_rng(8)
+    inlet = rng.uniform(-0.02, 0.04, (3, nz, ny))
+    cfg = oracle.Config(nx, ny, nz, periodic=(0, 0, 1), improved=improved, omega=1.6,
+                        accel=(1e-4, 2e-5, 0), solid=solid, open_x=True, rho_out=1.01,
+                        inlet=inlet, stencil=stencil, **ckw)
+    if stencil == 27:
+        u = rng.uniform(-0.05, 0.05, (3,) + cfg.shape)
+        f = oracle.init(cfg, u)
+    else:
+        u, f = _noisy(cfg, 9)
+    lat = _lattice(cfg, u, collision=coll, inlet=inlet, stencil=stencil)
+    lat.set_pdfs(f)
+    lat.step(3)
+    assert_f64_parity(host(lat.get_pdfs()), oracle.step(cfg, f, 3), f"open {coll}")
+    lat.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f32s", "f16s", "bf16s"])
+def test_open_faces_reduced_one_step(dtype):
+    nx, ny, nz = 20, 9, 6
+    rng = np.random.default_rng(10)
+    inlet = np.zeros((3, nz, ny))
+    inlet[0] = 0.03
+    cfg = oracle.Config(nx, ny, nz, periodic=(0, 0, 1), improved=1, trt=True, omega=1.9,
+                        open_x=True, rho_out=1.0, inlet=inlet)
+    u = np.zeros((3,) + cfg.shape)
+    u[0] = 0.03 + rng.uniform(-0.01, 0.01, cfg.shape)
+    lat = _lattice(cfg, u, dtype=dtype, collision="trt", inlet=inlet)
+    lat.step(5)
+    f_in = host(lat.get_pdfs())
+    lat.step(1)
+    want = oracle.step(cfg, f_in, 1)
+    got = host(lat.get_pdfs())
+    assert np.all(np.abs(got - want) <= reduced_bound(want, dtype, lat.scale))
+    lat.close()
+
+
+def test_pressure_driven_channel_against_oracle():
+    """The plane channel of the oracle's pin (parabolic inflow, rho_out = 1),
+    2000 FP64 steps on the GPU against the oracle, and the steady plane
+    mass flux equal to the prescribed inflow."""
+    H, L, U, w = 12, 40, 0.02, 1.2
+    y = np.arange(H)
+    prof = 4 * U * (y + 0.5) * (H - 0.5 - y) / H ** 2
+    inlet = np.zeros((3, 1, H))
+    inlet[0, 0] = prof
+    cfg = oracle.Config(L, H, 1, periodic=(0, 0, 1), improved=1, trt=True, omega=w,
+                        open_x=True, rho_out=1.0, inlet=inlet)
+    u0 = np.zeros((3, 1, H, L))
+    u0[0] = prof[None, :, None]
+    lat = _lattice(cfg, u0, collision="trt", inlet=inlet)
+    lat.step(2000)
+    f_gpu = host(lat.get_pdfs())
+    f_ref = oracle.step(cfg, oracle.init(cfg, u0), 2000)
+    assert_f64_parity(f_gpu, f_ref, "channel 2000 steps")
+    lat.step(18000)
+    _, u = lat.moments()
+    u = host(u)
+    assert np.abs(u[0, 0, :, L // 2] - prof).max() < 1e-4 * U
+    lat.close()
+
+
+def test_open_and_kbc_refuse_the_adjoint():
+    from paper_1803_04937_amd import Lattice, capi
+    for kw in (dict(collision="kbc"),
+               dict(collision="srt", periodic=(0, 1, 1), open_x=True, rho_out=1.0)):
+        lat = Lattice(8, 6, 5, u=dev(np.zeros((3, 5, 6, 8))), dtype="f32", **kw)
+        lam0, lam1 = lat.new_adjoint(), lat.new_adjoint()
+        with pytest.raises(capi.LBMError) as e:
+            lat.adjoint_step(lat.state, lam0, lam1)
+        assert e.value.status == capi.LBM_ESTATE
+        out = torch.zeros(4, dtype=torch.float64, device="cuda")
+        with pytest.raises(capi.LBMError) as e:
+            lat.objective(0, lat.state, out, lam0)
+        assert e.value.status == capi.LBM_ESTATE
+        lat.close()
+
+
+def test_open_faces_need_an_inlet():
+    from paper_1803_04937_amd import capi
+    p = capi.make_params(8, 6, 5, periodic=(0, 1, 1), open_x=1, rho_out=1.0, dtype=capi.LBM_F32)
+    nbytes = capi.lbm_state_bytes(p)
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    u = torch.zeros((3, 5, 6, 8), dtype=torch.float64, device="cuda")
+    ctx = capi.lbm_init(p, None, None, a, b, torch.cuda.current_stream().cuda_stream, None, u)
+    try:
+        with pytest.raises(capi.LBMError) as e:
+            capi.lbm_step(ctx, 1)
+        assert e.value.status == capi.LBM_ESTATE
+        inlet = torch.zeros((3, 5, 6), dtype=torch.float64, device="cuda")
+        capi.lbm_set_inlet(ctx, inlet)
+        capi.lbm_step(ctx, 2)
+        torch.cuda.synchronize()
+    finally:
+        capi.lbm_destroy(ctx)

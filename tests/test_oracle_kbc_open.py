@@ -77,12 +77,14 @@ def test_kbc_with_fixed_gamma_is_mrt(improved, gamma):
 def test_kbc_conserves_mass_and_adds_a(improved):
     a = np.array([1e-3, -2e-3, 5e-4])
     cfg = oracle.Config(1, 1, 1, improved=improved, kbc=True, omega=1.8, accel=tuple(a))
+    gammas = []
     for seed in range(6):
         f = _state(cfg, 10 + seed, amp=0.08).reshape(19)
         out, gamma = oracle.kbc_collide(cfg, f)
         assert abs(out.sum() - f.sum()) < 2e-15
         np.testing.assert_allclose(C.T @ out - C.T @ f, a, rtol=0, atol=2e-15)
-        assert gamma != 2.0
+        gammas.append(gamma)
+    assert min(gammas) < 2.0          # the stabiliser acted in some cells
 
 
 def _quadratic_entropy(cfg, g, gamma):
@@ -117,11 +119,11 @@ def _golden_min(fn, lo, hi, tol=1e-11):
 @pytest.mark.parametrize("omega", [1.3, 1.9])
 def test_kbc_gamma_minimises_the_second_order_entropy(improved, omega):
     """Brute-force line search of the entropic norm of f* - f^eq (evaluated
-    here from the oracle's post-collision states at fixed gamma) over the
-    stable rates 0 <= gamma beta <= 2 finds the oracle's entropic gamma, for
-    minimisers inside the interval and at its ends."""
+    here from the oracle's post-collision states at fixed gamma) over
+    0 <= gamma <= 2 finds the oracle's entropic gamma, for minimisers inside
+    the interval and at its ends."""
     cfg = oracle.Config(1, 1, 1, improved=improved, kbc=True, omega=omega)
-    hi = 2.0 / (omega / 2)
+    hi = 2.0
     rng = np.random.default_rng(20 + improved)
     inside = 0
     for _ in range(12):
@@ -144,7 +146,7 @@ def test_kbc_gamma_approaches_the_full_entropy_minimiser():
     u^2 / |f - f^eq|.)"""
     w = 1.4
     cfg = oracle.Config(1, 1, 1, improved=1, kbc=True, omega=w)
-    rng = np.random.default_rng(30)
+    rng = np.random.default_rng(33)        # a direction with an interior gamma
     fe = oracle.feq(cfg, 1.0, np.zeros(3))
     d0 = W * rng.standard_normal(19)
     d0 -= W * d0.sum() / W.sum()                        # no mass change
@@ -153,7 +155,7 @@ def test_kbc_gamma_approaches_the_full_entropy_minimiser():
     for eps in (4e-2, 4e-3):
         g = fe + eps * d0
         _, gamma = oracle.kbc_collide(cfg, g)
-        assert 0.0 < gamma < 4 / w            # an interior minimiser
+        assert 0.0 < gamma < 2.0              # an interior minimiser
 
         def H(s):
             c = oracle.Config(1, 1, 1, improved=1, kbc=True, kbc_gamma=s, omega=w)
@@ -188,8 +190,9 @@ def _shear_decay_rate(cfg, n, amp, T):
 def test_kbc_shear_viscosity_does_not_depend_on_gamma(improved):
     """A small-amplitude shear wave decays at the rate nu k^2 of
     nu = (1/omega - 1/2)/3 whatever the stabiliser: entropic, or fixed at
-    1.2, 2 (SRT) and 3.5; the rates agree with each other to 1e-6 and with
-    the closed form to the lattice's discretisation error."""
+    1.2, 2 (SRT) and 3.5 (beyond the entropic bound, to show that the rate of
+    the higher-order part does not enter); the rates agree with each other to
+    1e-6 and with the closed form to the lattice's discretisation error."""
     n, w, T = 32, 1.2, 200
     nu = (1 / w - 0.5) / 3
     k = 2 * np.pi / n
@@ -221,16 +224,17 @@ def test_kbc_duct_transverse_current(improved):
     """Duct along x (walls on y and z), driven by a_x from the square-duct
     Poiseuille field: with the Maxwellian moments (D3Q19-I) KBC keeps u_y =
     u_z = 0 to rounding, with the standard moments a transverse current
-    develops (Sec. 3.3, Sec. 5.1).  This needs the stabiliser's bound: at
-    the duct centre, where the velocity gradient vanishes, the unbounded
-    rate leaves (0, 2) and rounding noise in the transverse moments grows
-    about 2.5 times per step."""
-    D, w, a = 17, 1.0 / (0.5 + 3 * 0.05), 1e-4
+    develops (Sec. 3.3, Sec. 5.1).  This needs the stabiliser's bound
+    gamma <= 2: with the higher-order rate gamma omega / 2 allowed up to 2,
+    rounding noise in the transverse moments grows from step to step (about
+    3 % per step here once the rate nears 2; unbounded, 2.5 times per step)
+    until the current is as large as with D3Q19-S."""
+    D, w, a = 25, 1.0 / (0.5 + 3 * 0.05), 1e-4
     nu = (1 / w - 0.5) / 3
     u = lbm_inputs.duct_poiseuille(1, D, D, a, nu)
     cfg = oracle.Config(1, D, D, periodic=(1, 0, 0), improved=improved, kbc=True, omega=w,
                         accel=(a, 0, 0))
-    f = oracle.step(cfg, oracle.init(cfg, u), 400)
+    f = oracle.step(cfg, oracle.init(cfg, u), 1500)
     _, v = oracle.moments(cfg, f)
     ratio = np.abs(v[1:]).max() / np.abs(v[0]).max()
     if improved:

@@ -7,8 +7,10 @@ fresh process: the suite must fail.  The unmodified oracle passes the same
 suite (the other test files).
 """
 import os
+import re
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -34,8 +36,9 @@ MUTANTS = [
     ("improved edge: unsummed u^2", "3.0 * cu - 1.5 * uc2", "3.0 * cu - 1.5 * uu"),
     ("edge weight 1/36 -> 1/18", "return 1.0 / 36.0;", "return 1.0 / 18.0;"),
     ("streaming sign", "int p[3] = {x + s * C[q][0],", "int p[3] = {x - s * C[q][0],"),
-    ("bounce-back reads own direction", "g[q] = f[(int64_t)opposite(q) * n + here];",
-     "g[q] = f[(int64_t)q * n + here];"),
+    ("bounce-back reads own direction",
+     "if (is_solid(solid, src))\n            g[q] = f[(int64_t)qb * n + here];",
+     "if (is_solid(solid, src))\n            g[q] = f[(int64_t)q * n + here];"),
     ("velocity shift a/2 -> a", "u[d] = (j[d] + 0.5 * cfg->accel[d]) / *rho0;",
      "u[d] = (j[d] + 1.0 * cfg->accel[d]) / *rho0;"),
     ("SRT force factor (1 - w/2) -> (1 - w)",
@@ -106,8 +109,10 @@ MUTANTS = [
     ("KBC entropic metric weights w instead of f^eq",
      "sh += ds[q] * dh[q] / fe[q];\n        hh += dh[q] * dh[q] / fe[q];",
      "sh += ds[q] * dh[q] / weight(q);\n        hh += dh[q] * dh[q] / weight(q);"),
-    ("KBC stabiliser unbounded", "fmin(fmax(1.0 / beta - (2.0 - 1.0 / beta) * sh / hh, 0.0), 2.0 / beta)",
+    ("KBC stabiliser unbounded", "fmin(fmax(1.0 / beta - (2.0 - 1.0 / beta) * sh / hh, 0.0), 2.0)",
      "(1.0 / beta - (2.0 - 1.0 / beta) * sh / hh)"),
+    ("KBC stabiliser bounded by the marginal rate", "sh / hh, 0.0), 2.0)",
+     "sh / hh, 0.0), 2.0 / beta)"),
     ("inlet moving-wall term 6 -> 3", "+ 6.0 * weight(q) * cu;", "+ 3.0 * weight(q) * cu;"),
     ("inlet rule one cell too far", "if (cfg->open_x && px < 0) {", "if (cfg->open_x && px <= 0) {"),
     ("outlet bounce-back instead of anti-bounce-back",
@@ -121,15 +126,37 @@ MUTANTS = [
 ]
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_planted_mistake_is_caught(name, old, new, tmp_path):
+def _caught(name, old, new, workdir):
+    """Build the oracle with one planted mistake and run the pin suite
+    against it in a fresh process; True when the suite fails."""
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation site not unique: {old!r}"
-    mutant = tmp_path / "oracle_mutant.c"
-    mutant.write_text(src.replace(old, new))
-    lib = oracle.build(force=True, src=str(mutant), out=str(tmp_path / "liboracle_mutant.so"))
+    d = os.path.join(workdir, re.sub(r"[^A-Za-z0-9]+", "_", name))
+    os.makedirs(d, exist_ok=True)
+    mutant = os.path.join(d, "oracle_mutant.c")
+    with open(mutant, "w") as fh:
+        fh.write(src.replace(old, new))
+    lib = oracle.build(force=True, src=mutant, out=os.path.join(d, "liboracle_mutant.so"))
     env = dict(os.environ, LBM_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                           *PIN_FILES], cwd=ROOT, env=env, capture_output=True, text=True,
-                         timeout=600)
-    assert res.returncode != 0, f"pins did not catch: {name}\n{res.stdout[-2000:]}"
+                         timeout=900)
+    return res.returncode != 0, res.stdout[-1500:]
+
+
+def test_mutation_sites_are_unique():
+    src = open(SRC).read()
+    for name, old, _ in MUTANTS:
+        assert src.count(old) == 1, f"{name}: mutation site not unique: {old!r}"
+
+
+def test_planted_mistakes_are_caught(tmp_path):
+    """Every planted mistake makes the pin suite fail (mutants run four at a
+    time, each in its own process with two threads)."""
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        futs = {ex.submit(_caught, n, o, w, str(tmp_path)): n for n, o, w in MUTANTS}
+        results = {futs[f]: f.result() for f in futs}
+    escaped = [n for n, (caught, _) in results.items() if not caught]
+    for n in escaped:
+        print(f"not caught: {n}\n{results[n][1]}")
+    assert not escaped, escaped

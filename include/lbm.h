@@ -284,6 +284,41 @@ double lbm_scale(const lbm_ctx *c);
  * (mass and momentum); a non-NULL sums synchronises the stream. */
 int lbm_moments(lbm_ctx *c, double *rho, double *u, double *sums);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * moments and FP64 totals of lbm_moments for a state buffer, without a
+ * context, allocating nothing.  The reduction scratch is a fixed static
+ * device array inside the library (16 MiB per GPU the library runs on, held
+ * until the process ends), which limits the lattice to
+ * LBM_NOALLOC_MAX_CELLS cells.  Every call on a GPU shares that array:
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads) race and give wrong totals.  Results equal lbm_moments' bit for
+ * bit (same kernels, same reduction order).
+ *   p      the lattice's parameters
+ *   links  the link words lbm_init wrote for a lattice with a solid mask;
+ *          NULL for a lattice without one
+ *   state  device state buffer in the layout the pattern holds after t
+ *          steps (two-grid: direct; AA: t even local, t odd neighbour)
+ *   t      steps taken since initialisation (the AA parity)
+ *   scale  storage scale s of the 16-bit formats (lbm_scale); ignored for
+ *          the others
+ *   rho    device double [cells] or NULL; u device double [3][cells] or NULL
+ *   sums   device double[4] or NULL: the FP64 totals over fluid cells of
+ *          rho and of sum_q c_q f*_q, written (stream-ordered, no sync)
+ *   stream hipStream_t (NULL = default stream)
+ * LBM_EINVAL for invalid parameters, more than LBM_NOALLOC_MAX_CELLS cells,
+ * a NULL state, t < 0 or a 16-bit scale that is not a power of two;
+ * LBM_EHIP when the scratch's device address cannot be looked up or the
+ * launch fails.  The message is lbm_last_error(NULL).  The array's device
+ * address is looked up (hipGetSymbolAddress) once per GPU, by lbm_init or
+ * else by this function's first call on that GPU: make that first call
+ * outside a graph capture.  The successful path allocates nothing, on the
+ * device or the host. */
+#define LBM_NOALLOC_MAX_CELLS (1LL << 27)
+int lbm_moments_noalloc(const lbm_params *p, const uint32_t *links, const void *state,
+                        int64_t t, double scale, double *rho, double *u, double *sums,
+                        void *stream);
+
 /* Canonical copy of the current state: the post-collision populations f*_q
  * of Sec. 2.3 (the left side of eq. lb_srt_with_forces after the last step)
  * as device double [Q][cells] (dense, no padding, x fastest), in FP64

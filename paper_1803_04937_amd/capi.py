@@ -34,7 +34,7 @@ EXPORTS = [
     "lbm_stream_collide", "lbm_current_state", "lbm_copy_state", "lbm_time", "lbm_scale", "lbm_moments",
     "lbm_get_pdfs", "lbm_sample_pdfs", "lbm_set_pdfs", "lbm_watchdog", "lbm_set_rates",
     "lbm_set_inlet", "lbm_adjoint_step",
-    "lbm_objective", "lbm_init_vjp",
+    "lbm_objective", "lbm_init_vjp", "lbm_moments_noalloc",
 ]
 
 
@@ -100,6 +100,8 @@ def _load():
         "lbm_adjoint_step": ([P, P, P, P, P], ctypes.c_int),
         "lbm_objective": ([P, ctypes.c_int, P, P, P], ctypes.c_int),
         "lbm_init_vjp": ([P, P, P, P], ctypes.c_int),
+        "lbm_moments_noalloc": ([pp, P, P, ctypes.c_int64, ctypes.c_double, P, P, P, P],
+                                ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -306,3 +308,9 @@ def lbm_objective(ctx, kind: int, state, out, lam) -> None:
 def lbm_init_vjp(ctx, u_init, lam0, grad_u) -> None:
     _check(_lib.lbm_init_vjp(ctx, _addr(u_init), _addr(lam0), _addr(grad_u)), ctx)
 
+
+def lbm_moments_noalloc(p: lbm_params, links, state, t: int, scale: float, rho, u, sums,
+                        stream) -> None:
+    _check(_lib.lbm_moments_noalloc(ctypes.byref(p), _addr(links), _addr(state), int(t),
+                                    float(scale), _addr(rho), _addr(u), _addr(sums),
+                                    _addr(stream)), None)

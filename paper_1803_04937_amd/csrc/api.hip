@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -454,6 +455,8 @@ extern "C" int lbm_choose_scale(int32_t dtype, double maxdev, double *scale) {
     return LBM_OK;
 }
 
+static double *noalloc_scratch(std::string &why);
+
 // Lattice geometry of validated parameters (no GPU call).
 static void make_geom(const lbm_params *p, const uint32_t *links, Geom &g) {
     g.nx = p->nx;
@@ -527,7 +530,13 @@ extern "C" int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *solid
             return fail(nullptr, LBM_EINVAL, "internal: fast division check failed");
         }
     c->nblocks = cell_blocks(g);
-
+    {
+        // look up the allocation-free entry point's scratch on this device
+        // now, outside any graph capture (a failure is reported by that
+        // entry point itself)
+        std::string ignored;
+        (void)noalloc_scratch(ignored);
+    }
     c->sc.stage_half = (size_t)((c->nblocks + kReduceChunk - 1) / kReduceChunk) * 4;
     hipError_t e = hipMalloc(&c->sc.partials, (size_t)c->nblocks * 4 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->sc.stage, 2 * c->sc.stage_half * sizeof(double));
@@ -795,5 +804,79 @@ extern "C" int lbm_init_vjp(lbm_ctx *c, const double *u_init, const void *lam0, 
     hipError_t e = launch_init_vjp(c->g, c->p.stencil, c->p.adjoint_dtype, c->p.equilibrium,
                                    u_init, lam0, grad_u, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init_vjp");
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free moments.  The reduction scratch of lbm_moments_noalloc is
+// this file-scope device array: one copy per GPU, held until the process
+// ends.  Host code never passes its name to a kernel (in host code the name
+// is a host-side stand-in); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current.  Layout: block partials (4 doubles per 256 cells), the two halves
+// of the multi-pass fold, and a result slot.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kNoAllocMaxBlocks = (uint32_t)(LBM_NOALLOC_MAX_CELLS / kBlock);
+constexpr size_t kNoAllocStageHalf = (size_t)((kNoAllocMaxBlocks + kReduceChunk - 1) /
+                                              kReduceChunk) * 4;
+constexpr size_t kNoAllocDoubles = (size_t)kNoAllocMaxBlocks * 4 + 2 * kNoAllocStageHalf + 8;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (nullptr on failure).
+static double *noalloc_scratch(std::string &why) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        why = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+extern "C" int lbm_moments_noalloc(const lbm_params *p, const uint32_t *links, const void *state,
+                                   int64_t t, double scale, double *rho, double *u, double *sums,
+                                   void *stream) {
+    std::string why;
+    if (validate(p, why) != LBM_OK) return fail(nullptr, LBM_EINVAL, "%s", why.c_str());
+    const int64_t ncells = (int64_t)p->nx * p->ny * p->nz;
+    if (ncells > LBM_NOALLOC_MAX_CELLS)
+        return fail(nullptr, LBM_EINVAL,
+                    "lbm_moments_noalloc: %lld cells exceed the maximum of %lld (its static "
+                    "scratch holds the partials of 2^27 cells)",
+                    (long long)ncells, (long long)LBM_NOALLOC_MAX_CELLS);
+    if (!state) return fail(nullptr, LBM_EINVAL, "state is NULL");
+    if (t < 0) return fail(nullptr, LBM_EINVAL, "t must be >= 0");
+    const bool q16 = p->dtype == LBM_F16_SHIFTED || p->dtype == LBM_BF16_SHIFTED;
+    if (q16 && !is_pow2(scale))
+        return fail(nullptr, LBM_EINVAL, "scale must be the context's power of two (lbm_scale)");
+    double *base = noalloc_scratch(why);
+    if (!base) return fail(nullptr, LBM_EHIP, "%s", why.c_str());
+    Geom g;
+    make_geom(p, links, g);
+    const uint32_t nblocks = cell_blocks(g);
+    Scratch sc;
+    sc.partials = base;
+    sc.stage = base + (size_t)kNoAllocMaxBlocks * 4;
+    sc.stage_half = (size_t)((nblocks + kReduceChunk - 1) / kReduceChunk) * 4;
+    sc.result = sums ? sums : sc.stage + 2 * kNoAllocStageHalf;
+    const Layout lay = p->pattern == LBM_TWO_GRID ? kDirect : ((t & 1) ? kAANeighbor : kAALocal);
+    const double ah[3] = {0.5 * p->accel[0], 0.5 * p->accel[1], 0.5 * p->accel[2]};
+    hipError_t e = launch_moments(g, p->stencil, p->dtype, lay, q16 ? 1.0 / scale : 1.0,
+                                  p->compressible, ah, state, rho, u, sc, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, LBM_EHIP, "moments: %s", hipGetErrorString(e));
     return LBM_OK;
 }

@@ -4,7 +4,9 @@ the oracle and the seeded input generators):
 
 * 256^3 random-phase shear waves, omega = 1.95, 1000 steps, D3Q19-S SRT and
   D3Q19-I TRT (Lambda = 3/16), two-grid and AA: every PDF of ~530 sampled
-  cells within 1e-12 max(|f|, w_q) of the oracle's.
+  cells against the oracle's (1e-12 max(|f|, w_q), plus the measured growth
+  of rounding-size perturbations where the flow amplifies them), and
+  one-step parity from the GPU's own state along the trajectory.
 * The 512 x 128 x 128 duct (x periodic, walls on y and z), D3Q19-I SRT,
   omega = 1.9, g_x = 1e-6, T = 500: the FP64 GPU objective against the
   oracle's, and the FP32 checkpointed adjoint gradient (g_x, omega and a
@@ -36,23 +38,57 @@ def _npz(name):
 @pytest.mark.parametrize("pattern", ["two_grid", "aa"])
 @pytest.mark.parametrize("model", ["S_srt", "I_trt"])
 def test_shear256_fp64_1000_steps(model, pattern):
+    """One-step parity with the oracle along the trajectory (t = 0, 500 and
+    999, from the GPU's own state, at 1e-12 max(|f|, w_q)) and the state
+    after 1000 steps against the oracle's.  The latter allows, besides the
+    1e-12 bound, ten times the spread that a 1e-15 relative perturbation of
+    the initial state shows after the same 1000 GPU steps: D3Q19-I TRT at
+    omega = 1.95 (omega_minus = 0.066 at Lambda = 3/16) amplifies
+    perturbations of this field about 1.8 % per step (1e-15 grows to ~1e-7),
+    so the rounding differences of any two correct implementations grow
+    alike; D3Q19-S SRT does not amplify them and keeps the plain bound."""
+    import oracle
     from paper_1803_04937_amd import Lattice
     z = _npz(f"c2_256_w195_{model}.npz")
     meta = json.loads(str(z["meta"]))
     cells, want = z["cells"], z["pdfs"]
-    n = meta["n"]
-    u0 = lbm_inputs.shear_waves((n, n, n), seed=4)
-    lat = Lattice(n, n, n, u=dev(u0), equilibrium=meta["equilibrium"],
-                  collision=meta["collision"], omega=meta["omega"], trt_magic=meta["magic"],
-                  dtype="f64", pattern=pattern)
+    n, T = meta["n"], meta["steps"]
+    cfg = oracle.Config(n, n, n, improved=1 if meta["equilibrium"] == "improved" else 0,
+                        trt=meta["collision"] == "trt", omega=meta["omega"], magic=meta["magic"])
+    u0 = dev(lbm_inputs.shear_waves((n, n, n), seed=4))
+    kw = dict(equilibrium=meta["equilibrium"], collision=meta["collision"], omega=meta["omega"],
+              trt_magic=meta["magic"], dtype="f64", pattern=pattern)
+    lat = Lattice(n, n, n, u=u0, **kw)
+    pert = Lattice(n, n, n, u=u0, **kw)
     del u0
-    lat.step(meta["steps"])
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    f0 = pert.get_pdfs()
+    pert.set_pdfs(f0 * (1 + 1e-15 * torch.randn(f0.shape, generator=gen, device="cuda",
+                                                   dtype=torch.float64)))
+    del f0
+    t = 0
+    worst_step = 0.0
+    for t_check in (0, 500, T - 1):
+        lat.step(t_check - t)
+        f_in = host(lat.get_pdfs())
+        lat.step(1)
+        t = t_check + 1
+        got = host(lat.sample_pdfs(cells))
+        ref = oracle.step_cells(cfg, f_in, cells)
+        del f_in
+        worst_step = max(worst_step, (np.abs(got - ref) / np.maximum(np.abs(ref), W[None])).max())
+    pert.step(T)
+    assert lat.time == T
     got = host(lat.sample_pdfs(cells))
+    spread = np.abs(got - host(pert.sample_pdfs(cells))).max()
     lat.close()
-    bound = 1e-12 * np.maximum(np.abs(want), W[None, :])
+    pert.close()
+    bound = 1e-12 * np.maximum(np.abs(want), W[None, :]) + 10 * spread
     worst = (np.abs(got - want) / bound).max()
-    print(f"\nshear256 {model} {pattern}: worst {worst:.3f} x the 1e-12 bound, "
-          f"max abs err {np.abs(got - want).max():.2e}")
+    print(f"\nshear256 {model} {pattern}: one-step parity along the trajectory "
+          f"{worst_step:.2e}; after {T} steps max err {np.abs(got - want).max():.2e}, "
+          f"perturbation spread {spread:.2e}, worst {worst:.3f} x bound")
+    assert worst_step <= 1e-12
     assert worst <= 1.0
 
 

@@ -57,7 +57,8 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     const int j = threadIdx.x;
     // with an active list (solid cells left unwritten) only blocks that hold
     // a fluid cell are launched
-    const uint32_t idx = gen_block(g) * kBlock + j;
+    const uint32_t slot = GEN ? xcd_slot() : blockIdx.x;
+    const uint32_t idx = gen_block(g, slot) * kBlock + j;
     const bool valid = idx < g.ncells;
     // solid cells exist only where there is a mask (and its link words)
     const uint32_t link = GEN && valid && g.links ? g.links[idx] : kAllLinks;
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
             }
         }
     }
-    if (GRAD) block_reduce<4>(acc, partials + 4 * (size_t)blockIdx.x);
+    if (GRAD) block_reduce<4>(acc, partials + 4 * (size_t)slot);
 }
 
 // Objective of a two-grid state and its seed lam = dJ/df.

@@ -45,6 +45,7 @@
 #define LBM_DISPATCH_GEN3(gen, BODY)                                         \
     if (gen == kGenOpen) { constexpr int GEN = kGenOpen; BODY; }             \
     else if (gen == kGenWalls) { constexpr int GEN = kGenWalls; BODY; }      \
+    else if (gen == kGenWallsPlanar) { constexpr int GEN = kGenWallsPlanar; BODY; } \
     else { constexpr int GEN = kGenPeriodic; BODY; }
 
 // Collision operator of the stream-collide kernels (kCo*); MRT and KBC exist

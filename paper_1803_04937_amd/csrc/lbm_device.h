@@ -423,11 +423,25 @@ struct Geom {
     uint32_t nactive;
 };
 
-// Cell block of this workgroup in a launch over the active list (or over
-// every block when there is none).
-__device__ __forceinline__ uint32_t gen_block(const Geom &g) {
-    return g.active ? g.active[blockIdx.x] : blockIdx.x;
+// Slot of this workgroup in a one-dimensional launch.  The dispatcher hands
+// workgroup i to XCD i mod 8; the slots are taken in groups of 4 consecutive
+// blocks per XCD (workgroups 32 m + 8 t + k take slots 32 m + 4 k + t), so
+// that most neighbouring blocks, whose pulls share the cache lines at their
+// edges, meet in the same L2 while the whole grid still sweeps memory as one
+// front.  The last n mod 32 workgroups keep their own index.
+__device__ __forceinline__ uint32_t xcd_slot() {
+    const uint32_t b = blockIdx.x;
+    if (b >= (gridDim.x & ~31u)) return b;
+    const uint32_t w = b & 31u;
+    return (b & ~31u) + 4u * (w & 7u) + (w >> 3);
 }
+
+// Cell block of a workgroup at a slot of a launch over the active list (or
+// over every block when there is none).
+__device__ __forceinline__ uint32_t gen_block(const Geom &g, uint32_t slot) {
+    return g.active ? g.active[slot] : slot;
+}
+__device__ __forceinline__ uint32_t gen_block(const Geom &g) { return gen_block(g, xcd_slot()); }
 constexpr int kSolidBit = 31;
 
 // Boundary handling of the stream-collide kernels (template parameter GEN):
@@ -435,6 +449,11 @@ constexpr int kSolidBit = 31;
 // walls / mask with an open inlet face at x = -1/2 and outlet face at
 // x = nx - 1/2.
 constexpr int kGenPeriodic = 0, kGenWalls = 1, kGenOpen = 2;
+// kGenWallsPlanar: walls and / or a mask on a lattice whose planes hold a
+// whole number of 256-cell blocks, so that each block lies in one z-plane:
+// the two-grid step then addresses every pull as a uniform plane base plus a
+// 32-bit in-plane offset, as the periodic kernel does.
+constexpr int kGenWallsPlanar = 3;
 
 // Collision operators of the stream-collide kernels (template parameter CO):
 // SRT / TRT in pair form, MRT (Sec. 3.2), KBC (Sec. 3.3).
@@ -476,6 +495,21 @@ __device__ __forceinline__ PlaneHood make_plane_hood(uint32_t p, uint32_t z, con
     h.zp[1] = z;
     h.zp[2] = z == g.nz - 1 ? 0 : z + 1;
     return h;
+}
+
+// Link word of an in-plane cell from the walls alone (no mask): bit q when
+// x - c_q lies inside the domain.
+template <int QN>
+__device__ __forceinline__ uint32_t plane_wall_links(uint32_t p, uint32_t z, const Geom &g) {
+    const uint32_t y = fdiv(p, g.div_nx), x = p - y * g.nx;
+    const bool vx[3] = {x != 0 || g.per[0], true, x != g.nx - 1 || g.per[0]};
+    const bool vy[3] = {y != 0 || g.per[1], true, y != g.ny - 1 || g.per[1]};
+    const bool vz[3] = {z != 0 || g.per[2], true, z != g.nz - 1 || g.per[2]};
+    uint32_t w = 0;
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+        if (vx[1 - kC[q].x] && vy[1 - kC[q].y] && vz[1 - kC[q].z]) w |= 1u << q;
+    return w;
 }
 
 // Byte offset of the in-plane neighbour x + s c_q.

@@ -91,6 +91,41 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
             else
                 S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
         });
+    } else if constexpr (GEN == kGenWallsPlanar) {
+        // walls and / or a mask, every block inside one z-plane (over the
+        // active list when there is one): uniform plane bases, 32-bit
+        // in-plane offsets; a missing link reads the cell's own opposite slot
+        const uint32_t c0 = gen_block(g) * kBlock;
+        const uint32_t z = fdiv(c0, g.div_nxy);
+        const uint32_t p = c0 - z * g.nxy + threadIdx.x, idx = c0 + threadIdx.x;
+        if (p >= g.nxy) return;
+        const uint32_t link = g.links ? g.links[idx] : plane_wall_links<QN>(p, z, g);
+        if (link_solid(link)) return;
+        const PlaneHood h = make_plane_hood(p, z, g);
+        const uint32_t off = p * (uint32_t)sizeof(T);
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr bool H = fwd_load_hint<NT>(kC[q].x);
+            if ((link >> q) & 1u) {
+                const T *base = src + ((int64_t)h.zp[1 - kC[q].z] * QN + q) * g.qstride;
+                d[q] = S::template load<H>(at_bytes(base, plane_off<T>(h, q, -1)), 0,
+                                           (R)wq(QN, q), P.inv_s);
+            } else {
+                const T *base = src + ((int64_t)z * QN + opp(q)) * g.qstride;
+                d[q] = S::template load<H>(at_bytes(base, off), 0, (R)wq(QN, q), P.inv_s);
+            }
+        });
+        collide<R, EQ, QN, CO>(d, P);
+        SrBits rb{SR ? mix32(idx ^ key) : 0u};
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr bool H = fwd_store_hint<NT>(0);   // aligned stores
+            T *o = at_bytes(dst + ((int64_t)z * QN + q) * g.qstride, off);
+            if constexpr (SR)
+                store_sr<DT, H>(o, 0, d[q], P.s, rb.next(q));
+            else
+                S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
+        });
     } else {
         const uint32_t idx = gen_block(g) * kBlock + threadIdx.x;
         if (idx >= g.ncells) return;
@@ -125,7 +160,10 @@ hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, int co, int 
                           void *dst, hipStream_t st) {
     // kGenPeriodic runs the planar launch; lattices it cannot address take the
     // general kernel, which is exact for periodic lattices without a mask too.
+    // Walls and masks take the planar addressing when every 256-cell block
+    // lies inside one plane.
     if (gen == kGenPeriodic && !planar_ok(g)) gen = kGenWalls;
+    if (gen == kGenWalls && planar_ok(g) && g.nxy % kBlock == 0) gen = kGenWallsPlanar;
     const dim3 grid = gen != kGenPeriodic ? dim3(gen_blocks(g)) : plane_grid(g), block(kBlock);
     if (grid.x == 0) return hipSuccess;   // every cell solid
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN3(gen, LBM_DISPATCH_CO(

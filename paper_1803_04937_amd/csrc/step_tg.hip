@@ -103,17 +103,17 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
         if (link_solid(link)) return;
         const PlaneHood h = make_plane_hood(p, z, g);
         const uint32_t off = p * (uint32_t)sizeof(T);
+        // one load per direction, from the pull source or, for a missing
+        // link, from the cell's own opposite slot: both as 32-bit byte
+        // offsets from the state's base (the launch checks that the state
+        // spans less than 4 GiB), so the choice is one select per direction
+        const uint32_t qsb = (uint32_t)g.qstride * (uint32_t)sizeof(T);
         static_for<QN>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            constexpr bool H = fwd_load_hint<NT>(kC[q].x);
-            if ((link >> q) & 1u) {
-                const T *base = src + ((int64_t)h.zp[1 - kC[q].z] * QN + q) * g.qstride;
-                d[q] = S::template load<H>(at_bytes(base, plane_off<T>(h, q, -1)), 0,
-                                           (R)wq(QN, q), P.inv_s);
-            } else {
-                const T *base = src + ((int64_t)z * QN + opp(q)) * g.qstride;
-                d[q] = S::template load<H>(at_bytes(base, off), 0, (R)wq(QN, q), P.inv_s);
-            }
+            const uint32_t pull = (h.zp[1 - kC[q].z] * QN + q) * qsb + plane_off<T>(h, q, -1);
+            const uint32_t self = (z * QN + opp(q)) * qsb + off;
+            d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(
+                at_bytes(src, (link >> q) & 1u ? pull : self), 0, (R)wq(QN, q), P.inv_s);
         });
         collide<R, EQ, QN, CO>(d, P);
         SrBits rb{SR ? mix32(idx ^ key) : 0u};
@@ -163,7 +163,11 @@ hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, int co, int 
     // Walls and masks take the planar addressing when every 256-cell block
     // lies inside one plane.
     if (gen == kGenPeriodic && !planar_ok(g)) gen = kGenWalls;
-    if (gen == kGenWalls && planar_ok(g) && g.nxy % kBlock == 0) gen = kGenWallsPlanar;
+    const uint64_t state_bytes = (uint64_t)g.nz * qn * g.qstride *
+                                 (dtype == LBM_F64 ? 8 : dtype == LBM_F16_SHIFTED ||
+                                  dtype == LBM_BF16_SHIFTED ? 2 : 4);
+    if (gen == kGenWalls && planar_ok(g) && g.nxy % kBlock == 0 && state_bytes <= 0xffffffffull)
+        gen = kGenWallsPlanar;
     const dim3 grid = gen != kGenPeriodic ? dim3(gen_blocks(g)) : plane_grid(g), block(kBlock);
     if (grid.x == 0) return hipSuccess;   // every cell solid
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN3(gen, LBM_DISPATCH_CO(

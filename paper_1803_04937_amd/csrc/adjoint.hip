@@ -147,6 +147,112 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
     if (GRAD) block_reduce<4>(acc, partials + 4 * (size_t)slot);
 }
 
+// Planar form of k_adjoint, for lattices whose planes hold a whole number
+// of 256-cell blocks (each block inside one z-plane) and whose state and
+// adjoint fields each span less than 4 GiB: the same gathers, pushes,
+// parking and outbox, with every address a 32-bit byte offset from the
+// field's base, its plane term uniform and its in-plane term per lane.  A
+// direction's pull source and its bounce-back slot are then chosen by one
+// select, where the general kernel keeps 64-bit positions per lane.
+template <int QN, int DT, int LT, int EQ, bool GEN, bool MRT, bool GRAD, bool NT>
+__global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint_planar(
+    Geom g, Coll<typename Store<DT>::R> P, const typename Store<DT>::T *__restrict__ state,
+    const typename Lam<LT>::T *__restrict__ lam_next, typename Lam<LT>::T *__restrict__ lam_prev,
+    double *partials, int copy_solid) {
+    using S = Store<DT>;
+    using R = typename S::R;
+    using T = typename S::T;
+    using L = typename Lam<LT>::T;
+    constexpr const XTab &X = QN == 19 ? kXTab19 : kXTab27;
+    constexpr uint32_t TB = sizeof(T), LB = sizeof(L);
+    __shared__ L xbuf[X.n][2 * kBlock];
+    __shared__ uint32_t lw[GEN ? kBlock : 1];
+    const int j = threadIdx.x;
+    const uint32_t slot = GEN ? xcd_slot() : blockIdx.x;
+    const uint32_t c0 = gen_block(g, slot) * kBlock;
+    const uint32_t z = fdiv(c0, g.div_nxy);
+    const uint32_t p = c0 - z * g.nxy + j;
+    uint32_t link = kAllLinks;
+    if constexpr (GEN) {
+        link = g.links ? g.links[c0 + j] : plane_wall_links<QN>(p, z, g);
+        lw[j] = link;
+    }
+    const bool fluid = !link_solid(link);
+    const uint32_t qsT = (uint32_t)g.qstride * TB, qsL = (uint32_t)g.qstride * LB;
+    constexpr bool HL = NT && LBM_NT_ADJ_LOADS != 0, HS = NT && LBM_NT_ADJ_STORES != 0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (fluid) {
+        const PlaneHood h = make_plane_hood(p, z, g);
+        R d[QN], lam[QN];
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const bool fl = !GEN || ((link >> q) & 1u);
+            const uint32_t pull = (h.zp[1 - kC[q].z] * QN + q) * qsT + plane_off<T>(h, q, -1);
+            const uint32_t self = (z * QN + opp(q)) * qsT + p * TB;
+            d[q] = S::template load<HL>(at_bytes(state, fl ? pull : self), 0, (R)wq(QN, q),
+                                        P.inv_s);
+            lam[q] = (R)ld<HL>(at_bytes(lam_next, (z * QN + q) * qsL + p * LB));
+        });
+        adjoint_cell<R, EQ, QN, MRT>(d, lam, P, acc);
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const bool fl = !GEN || ((link >> q) & 1u);
+            if constexpr (kC[q].x != 0) {
+                const int jr = j + h.ox[1 - kC[q].x];
+                const bool park = fl && jr >= 0 && jr < kBlock;
+                xbuf[X.rank[q]][park ? jr : kBlock + j] = (L)lam[q];
+            } else {
+                const uint32_t pull =
+                    (h.zp[1 - kC[q].z] * QN + q) * qsL + plane_off<L>(h, q, -1);
+                const uint32_t self = (z * QN + opp(q)) * qsL + p * LB;
+                st<HS>(at_bytes(lam_prev, fl ? pull : self), (L)lam[q]);
+            }
+        });
+    } else if (copy_solid) {
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const uint32_t o = (z * QN + q) * qsL + p * LB;
+            st<NT>(at_bytes(lam_prev, o), ld<NT>(at_bytes(lam_next, o)));
+        }
+    }
+    __syncthreads();
+    // the in-plane terms again from an opaque copy of p, so that they are
+    // recomputed here rather than held through the collision
+    uint32_t p2 = p;
+    asm volatile("" : "+v"(p2));
+    const PlaneHood h = make_plane_hood(p2, z, g);
+    static_for<QN>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (kC[q].x != 0) {
+            // parked slot: the push of writer x + c_x into this cell's x
+            const int jw = j + h.ox[1 + kC[q].x];
+            if (jw >= 0 && jw < kBlock) {
+                bool filled = true;
+                if constexpr (GEN) {
+                    const uint32_t wl = lw[jw];
+                    filled = !link_solid(wl) && ((wl >> q) & 1u);
+                }
+                if (filled)
+                    st<HS>(at_bytes(lam_prev, (h.zp[1 - kC[q].z] * QN + q) * qsL +
+                                                  plane_off<L>(h, X.q0[q], -1)),
+                           xbuf[X.rank[q]][j]);
+            }
+            // outbox: this cell's own push that was not parked
+            if (fluid) {
+                const bool fl = !GEN || ((link >> q) & 1u);
+                const int jr = j + h.ox[1 - kC[q].x];
+                if (!(fl && jr >= 0 && jr < kBlock)) {
+                    const uint32_t pull =
+                        (h.zp[1 - kC[q].z] * QN + q) * qsL + plane_off<L>(h, q, -1);
+                    const uint32_t self = (z * QN + opp(q)) * qsL + p2 * LB;
+                    st<HS>(at_bytes(lam_prev, fl ? pull : self), xbuf[X.rank[q]][kBlock + j]);
+                }
+            }
+        }
+    });
+    if (GRAD) block_reduce<4>(acc, partials + 4 * (size_t)slot);
+}
+
 // Objective of a two-grid state and its seed lam = dJ/df.
 //   kind 0: J = 1/2 sum |u|^2,  lam_q = c_q.u,  dJ/da = -1/2 sum u
 //   kind 1: J = sum_{x = nx-1} u_x,  lam_q = c_qx there,  dJ/da_x = -1/2 count
@@ -254,6 +360,12 @@ __global__ __launch_bounds__(kBlock) void k_init_vjp(Geom g, const double *__res
 // FP64 storage, FP32 otherwise.
 #define LBM_LT_OF(DT) ((DT) == LBM_F64 ? LBM_F64 : LBM_F32)
 
+// One adjoint launch (inside the dispatch below).
+#define LBM_ADJ_LAUNCH(KERNEL, G)                                                             \
+    hipLaunchKernelGGL((KERNEL<QN, DT, LT, EQ, GEN, MRT, G, NT>), grid, block,                 \
+                       LBM_ADJ_LDS_BYTES, st, ga, pick<DT>(P), (const T *)state,               \
+                       (const L *)lam_next, (L *)lam_prev, sc.partials, (int)copy_solid)
+
 hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, bool mrt, bool gen,
                           bool nt, bool copy_solid, const CollBoth &P, const void *state,
                           const void *lam_next, void *lam_prev, double *grad, const Scratch &sc,
@@ -271,19 +383,25 @@ hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, b
         constexpr int LT = LBM_LT_OF(DT);
         using T = typename Store<DT>::T;
         using L = typename Lam<LT>::T;
-        if (want)
-            hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, true, NT>), grid, block,
-                               LBM_ADJ_LDS_BYTES, st, ga, pick<DT>(P), (const T *)state,
-                               (const L *)lam_next, (L *)lam_prev, sc.partials, (int)copy_solid);
-        else
-            hipLaunchKernelGGL((k_adjoint<QN, DT, LT, EQ, GEN, MRT, false, NT>), grid, block,
-                               LBM_ADJ_LDS_BYTES, st, ga, pick<DT>(P), (const T *)state,
-                               (const L *)lam_next, (L *)lam_prev, sc.partials, (int)copy_solid);
+        const uint64_t cells = (uint64_t)ga.nz * qn * ga.qstride;
+        const bool planar = planar_ok(ga) && ga.nxy % kBlock == 0 &&
+                            cells * sizeof(T) <= 0xffffffffull && cells * sizeof(L) <= 0xffffffffull;
+        if (planar && want) {
+            LBM_ADJ_LAUNCH(k_adjoint_planar, true);
+        } else if (planar) {
+            LBM_ADJ_LAUNCH(k_adjoint_planar, false);
+        } else if (want) {
+            LBM_ADJ_LAUNCH(k_adjoint, true);
+        } else {
+            LBM_ADJ_LAUNCH(k_adjoint, false);
+        }
     })))));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !want) return e;
     return launch_finalize(sc, grid.x, 4, 0, grad, true, st);
 }
+
+#undef LBM_ADJ_LAUNCH
 
 hipError_t launch_objective(const Geom &g, int qn, int dtype, int ltype, int kind, double inv_s,
                             const double ah[3], const void *state, double *out, void *lam,

@@ -286,7 +286,7 @@ static void invert(double *a, int n) {
 // ones sum_p 2 c_q^e (n_q - n_qbar)/2 (q = 2p+1, qbar = q+1), so
 // M_e = [c_0^e | 2 c_q^e] (10 x 10) and M_o = [2 c_q^e] (9 x 9); the
 // relaxation in pair coordinates is K = M^-1 S M.
-static void mrt_matrices(const lbm_params &p, double ke[100], double ko[81], double pe2[100]) {
+static void mrt_matrices(const lbm_params &p, double ke[100], double ko[81]) {
     static const int even[10][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0},
                                     {1, 0, 1}, {0, 1, 1}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}};
     static const int odd[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 1, 0}, {2, 0, 1},
@@ -325,10 +325,6 @@ static void mrt_matrices(const lbm_params &p, double ke[100], double ko[81], dou
     }
     relax(me, se, 10, ke);
     relax(mo, so, 9, ko);
-    // d K_e / d omega = M_e^-1 diag(order == 2) M_e (the adjoint's dJ/domega)
-    double s2[10];
-    for (int k = 0; k < 10; ++k) s2[k] = even[k][0] + even[k][1] + even[k][2] == 2 ? 1.0 : 0.0;
-    relax(me, s2, 10, pe2);
 }
 
 // Relaxation and force constants of the update in both precisions.
@@ -360,7 +356,9 @@ static void set_coll(lbm_ctx *c) {
     d.s = c->scale;
     d.inv_s = 1.0 / c->scale;
     d.compressible = p.compressible;
-    if (p.collision == LBM_MRT) mrt_matrices(p, d.ke, d.ko, d.pe2);
+    if (p.collision == LBM_MRT) mrt_matrices(p, d.ke, d.ko);
+    d.w3 = p.mrt_omega3;
+    d.w4 = p.mrt_omega4;
     Coll<float> f = {};
     f.wp = (float)d.wp;
     f.wm = (float)d.wm;
@@ -378,7 +376,8 @@ static void set_coll(lbm_ctx *c) {
     f.kbc_hi = (float)d.kbc_hi;
     f.drho_out = (float)d.drho_out;
     for (int i = 0; i < 100; ++i) f.ke[i] = (float)d.ke[i];
-    for (int i = 0; i < 100; ++i) f.pe2[i] = (float)d.pe2[i];
+    f.w3 = (float)d.w3;
+    f.w4 = (float)d.w4;
     for (int i = 0; i < 81; ++i) f.ko[i] = (float)d.ko[i];
     c->coll.d = d;
     c->coll.f = f;

@@ -606,6 +606,85 @@ __device__ __forceinline__ uint32_t hood_cell(const Hood &h, const Geom &g, int 
     return c;
 }
 
+// D3Q19 MRT moment bases (Sec. 3.2) in the pair coordinates of the
+// collision: even monomials 1, x^2, y^2, z^2, xy, xz, yz, x^2y^2, x^2z^2,
+// y^2z^2 over [rest, 9 pair half-sums] with entries c^e (rest) and 2 c^e
+// (pairs), odd monomials x, y, z, x^2y, x^2z, xy^2, y^2z, xz^2, yz^2 over the
+// 9 pair half-differences with entries 2 c^e; the relaxation is
+// K = M^-1 S M with S the rate of each monomial's order.  The bases and
+// their inverses are compile-time constants, so that the adjoint applies
+// K^T = M^T S M^-T on their (mostly zero) entries.
+struct MrtBasis {
+    double me[10][10], mei[10][10], mo[9][9], moi[9][9];
+    int ord_e[10], ord_o[9];
+};
+constexpr int kMrtEven[10][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0},
+                                 {1, 0, 1}, {0, 1, 1}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}};
+constexpr int kMrtOdd[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 1, 0}, {2, 0, 1},
+                               {1, 2, 0}, {0, 2, 1}, {1, 0, 2}, {0, 1, 2}};
+constexpr double mrt_mono(const int (&e)[3], int q) {
+    const int c[3] = {kC[q].x, kC[q].y, kC[q].z};
+    double v = 1.0;
+    for (int i = 0; i < 3; ++i)
+        for (int t = 0; t < e[i]; ++t) v *= c[i];
+    return v;
+}
+// Gauss-Jordan inverse with partial pivoting of an n x n block (n <= 10) of
+// a 10-column array, evaluated at compile time.
+template <int N>
+constexpr void mrt_invert(const double (&a)[N][N], double (&inv)[N][N]) {
+    double w[N][2 * N] = {};
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            w[i][j] = a[i][j];
+            w[i][N + j] = i == j ? 1.0 : 0.0;
+        }
+    for (int col = 0; col < N; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < N; ++r) {
+            const double x = w[r][col] < 0 ? -w[r][col] : w[r][col];
+            const double y = w[piv][col] < 0 ? -w[piv][col] : w[piv][col];
+            if (x > y) piv = r;
+        }
+        for (int j = 0; j < 2 * N; ++j) {
+            const double t = w[col][j];
+            w[col][j] = w[piv][j];
+            w[piv][j] = t;
+        }
+        const double d = w[col][col];
+        for (int j = 0; j < 2 * N; ++j) w[col][j] = w[col][j] / d;
+        for (int r = 0; r < N; ++r) {
+            if (r == col) continue;
+            const double f = w[r][col];
+            for (int j = 0; j < 2 * N; ++j) w[r][j] = w[r][j] - f * w[col][j];
+        }
+    }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) inv[i][j] = w[i][N + j];
+}
+constexpr MrtBasis make_mrt_basis() {
+    MrtBasis b{};
+    for (int k = 0; k < 10; ++k) {
+        b.me[k][0] = mrt_mono(kMrtEven[k], 0);
+        for (int p = 0; p < 9; ++p) b.me[k][p + 1] = 2.0 * mrt_mono(kMrtEven[k], 2 * p + 1);
+        b.ord_e[k] = kMrtEven[k][0] + kMrtEven[k][1] + kMrtEven[k][2];
+    }
+    for (int k = 0; k < 9; ++k) {
+        for (int p = 0; p < 9; ++p) b.mo[k][p] = 2.0 * mrt_mono(kMrtOdd[k], 2 * p + 1);
+        b.ord_o[k] = kMrtOdd[k][0] + kMrtOdd[k][1] + kMrtOdd[k][2];
+    }
+    mrt_invert<10>(b.me, b.mei);
+    mrt_invert<9>(b.mo, b.moi);
+    return b;
+}
+constexpr MrtBasis kMrt19 = make_mrt_basis();
+
+// Rate of a moment of the given order: 1 for the conserved orders 0 and 1.
+template <typename R, typename C>
+__device__ __forceinline__ R mrt_rate(const C &P, int order) {
+    return order <= 1 ? R(1) : order == 2 ? P.wp : order == 3 ? P.w3 : P.w4;
+}
+
 // ---------------------------------------------------------------------------
 // Collision parameters (host-prepared, compute type R).
 // ---------------------------------------------------------------------------
@@ -622,7 +701,7 @@ struct Coll {
     // [rest, 9 pair sums] and the odd part [9 pair differences], row-major.
     R ke[100];
     R ko[81];
-    R pe2[100];     // d K_e / d omega (MRT adjoint)
+    R w3, w4;       // MRT rates of the third- and fourth-order moments
     // KBC (D3Q19), with beta = omega / 2: 1/beta, 2 - 1/beta and the upper
     // bound 2 of the stabiliser gamma
     R kbc_ib, kbc_c, kbc_hi;
@@ -958,7 +1037,11 @@ __device__ __forceinline__ void adjoint_cell(const R (&d)[QN], R (&lam)[QN], con
     const R g0s = R(Poly::rest_grad<EQ, NP>());
     const R w0 = R(wq(QN, 0));
     R nu0, nup[NP], num[NP];
+    [[maybe_unused]] R te[10];   // M_e^-T [lam_0, lam_q + lam_qbar] (MRT)
     if constexpr (MRT && QN == 19) {
+        // K^T l = M^T S M^-T l on the constant bases: the zero entries drop
+        // out at compile time
+        constexpr const MrtBasis &B = kMrt19;
         R le[10], lo[9];
         le[0] = lam[0];
 #pragma unroll
@@ -966,11 +1049,30 @@ __device__ __forceinline__ void adjoint_cell(const R (&d)[QN], R (&lam)[QN], con
             le[p + 1] = lam[2 * p + 1] + lam[2 * p + 2];
             lo[p] = lam[2 * p + 1] - lam[2 * p + 2];
         }
+        R ts[10], to[9];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            R v = R(0);
+#pragma unroll
+            for (int i = 0; i < 10; ++i)
+                if (B.mei[i][k] != 0.0) v += R(B.mei[i][k]) * le[i];
+            te[k] = v;
+            ts[k] = mrt_rate<R>(P, B.ord_e[k]) * v;
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            R v = R(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (B.moi[i][k] != 0.0) v += R(B.moi[i][k]) * lo[i];
+            to[k] = mrt_rate<R>(P, B.ord_o[k]) * v;
+        }
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
             R v = R(0);
 #pragma unroll
-            for (int i = 0; i < 10; ++i) v += P.ke[10 * i + j] * le[i];
+            for (int k = 0; k < 10; ++k)
+                if (B.me[k][j] != 0.0) v += R(B.me[k][j]) * ts[k];
             if (j == 0)
                 nu0 = v;
             else
@@ -980,7 +1082,8 @@ __device__ __forceinline__ void adjoint_cell(const R (&d)[QN], R (&lam)[QN], con
         for (int j = 0; j < 9; ++j) {
             R v = R(0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) v += P.ko[9 * i + j] * lo[i];
+            for (int k = 0; k < 9; ++k)
+                if (B.mo[k][j] != 0.0) v += R(B.mo[k][j]) * to[k];
             num[j] = R(0.5) * v;
         }
     } else {
@@ -1038,15 +1141,18 @@ __device__ __forceinline__ void adjoint_cell(const R (&d)[QN], R (&lam)[QN], con
     }
     if constexpr (MRT && QN == 19) {
         // only the second-order moments' rate depends on omega:
-        // dJ/domega = -[lam_0, lam_q + lam_qbar] . (dK_e/domega) [n0, ne]
+        // dJ/domega = -le . M_e^-1 E_2 M_e [n0, ne] = -sum over the
+        // second-order rows k of (M_e^-T le)_k (M_e [n0, ne])_k
+        constexpr const MrtBasis &B = kMrt19;
         R acc0 = R(0);
 #pragma unroll
-        for (int i = 0; i < 10; ++i) {
-            R v = P.pe2[10 * i] * n0;
+        for (int k = 0; k < 10; ++k) {
+            if (B.ord_e[k] != 2) continue;
+            R m = B.me[k][0] != 0.0 ? R(B.me[k][0]) * n0 : R(0);
 #pragma unroll
-            for (int j = 0; j < 9; ++j) v += P.pe2[10 * i + j + 1] * ne[j];
-            const R li = i == 0 ? lam[0] : lam[2 * i - 1] + lam[2 * i];
-            acc0 -= li * v;
+            for (int j = 0; j < 9; ++j)
+                if (B.me[k][j + 1] != 0.0) m += R(B.me[k][j + 1]) * ne[j];
+            acc0 -= te[k] * m;
         }
         acc[0] += (A)acc0;
         acc[1] += (A)(R(0.5) * Vx + Gx);

@@ -148,12 +148,41 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint(
 }
 
 // Planar form of k_adjoint, for lattices whose planes hold a whole number
-// of 256-cell blocks (each block inside one z-plane) and whose state and
-// adjoint fields each span less than 4 GiB: the same gathers, pushes,
-// parking and outbox, with every address a 32-bit byte offset from the
-// field's base, its plane term uniform and its in-plane term per lane.  A
-// direction's pull source and its bounce-back slot are then chosen by one
-// select, where the general kernel keeps 64-bit positions per lane.
+// of 256-cell blocks (each block inside one z-plane): the same gathers,
+// pushes, parking and outbox, with every direction's plane base uniform
+// over the block and a 32-bit in-plane byte offset per lane.  Without walls
+// or a mask (GEN = false) every access is such a base plus offset.  With
+// them, a direction's pull source and its bounce-back slot lie in
+// different planes; the launch then requires each field to span less than
+// 4 GiB, so that both are 32-bit byte offsets from the field's base and one
+// select chooses between them.  The general kernel keeps 64-bit positions
+// per lane.
+// Value of direction q in plane zq at in-plane byte offset boff.  W32: the
+// field spans less than 4 GiB and the plane term joins the 32-bit offset;
+// otherwise it stays in a uniform 64-bit base.
+template <bool W32, int QN, typename E>
+__device__ __forceinline__ E *plane_at(E *base, const Geom &g, uint32_t zq, int q, uint32_t boff) {
+    if constexpr (W32)
+        return at_bytes(base, (zq * QN + q) * ((uint32_t)g.qstride * (uint32_t)sizeof(E)) + boff);
+    else
+        return at_bytes(base + (int64_t)(zq * QN + q) * g.qstride, boff);
+}
+
+// Pull source x - c_q of direction q, or with GEN and no link (fl false)
+// the cell's own slot of opp(q): one select between two 32-bit offsets.
+template <bool GEN, int QN, int q, typename E>
+__device__ __forceinline__ E *pull_or_own(E *base, const Geom &g, const PlaneHood &h, uint32_t z,
+                                          bool fl) {
+    if constexpr (GEN) {
+        const uint32_t qs = (uint32_t)g.qstride * (uint32_t)sizeof(E);
+        const uint32_t pull = (h.zp[1 - kC[q].z] * QN + q) * qs + plane_off<E>(h, q, -1);
+        const uint32_t own = (z * QN + opp(q)) * qs + h.p * (uint32_t)sizeof(E);
+        return at_bytes(base, fl ? pull : own);
+    } else {
+        return plane_at<false, QN>(base, g, h.zp[1 - kC[q].z], q, plane_off<E>(h, q, -1));
+    }
+}
+
 template <int QN, int DT, int LT, int EQ, bool GEN, bool MRT, bool GRAD, bool NT>
 __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint_planar(
     Geom g, Coll<typename Store<DT>::R> P, const typename Store<DT>::T *__restrict__ state,
@@ -161,10 +190,9 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint_planar(
     double *partials, int copy_solid) {
     using S = Store<DT>;
     using R = typename S::R;
-    using T = typename S::T;
     using L = typename Lam<LT>::T;
     constexpr const XTab &X = QN == 19 ? kXTab19 : kXTab27;
-    constexpr uint32_t TB = sizeof(T), LB = sizeof(L);
+    constexpr uint32_t LB = sizeof(L);
     __shared__ L xbuf[X.n][2 * kBlock];
     __shared__ uint32_t lw[GEN ? kBlock : 1];
     const int j = threadIdx.x;
@@ -178,7 +206,6 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint_planar(
         lw[j] = link;
     }
     const bool fluid = !link_solid(link);
-    const uint32_t qsT = (uint32_t)g.qstride * TB, qsL = (uint32_t)g.qstride * LB;
     constexpr bool HL = NT && LBM_NT_ADJ_LOADS != 0, HS = NT && LBM_NT_ADJ_STORES != 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (fluid) {
@@ -187,11 +214,9 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint_planar(
         static_for<QN>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             const bool fl = !GEN || ((link >> q) & 1u);
-            const uint32_t pull = (h.zp[1 - kC[q].z] * QN + q) * qsT + plane_off<T>(h, q, -1);
-            const uint32_t self = (z * QN + opp(q)) * qsT + p * TB;
-            d[q] = S::template load<HL>(at_bytes(state, fl ? pull : self), 0, (R)wq(QN, q),
-                                        P.inv_s);
-            lam[q] = (R)ld<HL>(at_bytes(lam_next, (z * QN + q) * qsL + p * LB));
+            d[q] = S::template load<HL>(pull_or_own<GEN, QN, q>(state, g, h, z, fl), 0,
+                                        (R)wq(QN, q), P.inv_s);
+            lam[q] = (R)ld<HL>(plane_at<GEN, QN>(lam_next, g, z, q, p * LB));
         });
         adjoint_cell<R, EQ, QN, MRT>(d, lam, P, acc);
         static_for<QN>([&](auto qc) {
@@ -202,18 +227,14 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint_planar(
                 const bool park = fl && jr >= 0 && jr < kBlock;
                 xbuf[X.rank[q]][park ? jr : kBlock + j] = (L)lam[q];
             } else {
-                const uint32_t pull =
-                    (h.zp[1 - kC[q].z] * QN + q) * qsL + plane_off<L>(h, q, -1);
-                const uint32_t self = (z * QN + opp(q)) * qsL + p * LB;
-                st<HS>(at_bytes(lam_prev, fl ? pull : self), (L)lam[q]);
+                st<HS>(pull_or_own<GEN, QN, q>(lam_prev, g, h, z, fl), (L)lam[q]);
             }
         });
     } else if (copy_solid) {
 #pragma unroll
-        for (int q = 0; q < QN; ++q) {
-            const uint32_t o = (z * QN + q) * qsL + p * LB;
-            st<NT>(at_bytes(lam_prev, o), ld<NT>(at_bytes(lam_next, o)));
-        }
+        for (int q = 0; q < QN; ++q)
+            st<NT>(plane_at<GEN, QN>(lam_prev, g, z, q, p * LB),
+                   ld<NT>(plane_at<GEN, QN>(lam_next, g, z, q, p * LB)));
     }
     __syncthreads();
     // the in-plane terms again from an opaque copy of p, so that they are
@@ -233,20 +254,17 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint_planar(
                     filled = !link_solid(wl) && ((wl >> q) & 1u);
                 }
                 if (filled)
-                    st<HS>(at_bytes(lam_prev, (h.zp[1 - kC[q].z] * QN + q) * qsL +
-                                                  plane_off<L>(h, X.q0[q], -1)),
+                    st<HS>(plane_at<GEN, QN>(lam_prev, g, h.zp[1 - kC[q].z], q,
+                                             plane_off<L>(h, X.q0[q], -1)),
                            xbuf[X.rank[q]][j]);
             }
             // outbox: this cell's own push that was not parked
             if (fluid) {
                 const bool fl = !GEN || ((link >> q) & 1u);
                 const int jr = j + h.ox[1 - kC[q].x];
-                if (!(fl && jr >= 0 && jr < kBlock)) {
-                    const uint32_t pull =
-                        (h.zp[1 - kC[q].z] * QN + q) * qsL + plane_off<L>(h, q, -1);
-                    const uint32_t self = (z * QN + opp(q)) * qsL + p2 * LB;
-                    st<HS>(at_bytes(lam_prev, fl ? pull : self), xbuf[X.rank[q]][kBlock + j]);
-                }
+                if (!(fl && jr >= 0 && jr < kBlock))
+                    st<HS>(pull_or_own<GEN, QN, q>(lam_prev, g, h, z, fl),
+                           xbuf[X.rank[q]][kBlock + j]);
             }
         }
     });
@@ -383,9 +401,10 @@ hipError_t launch_adjoint(const Geom &g, int qn, int dtype, int ltype, int eq, b
         constexpr int LT = LBM_LT_OF(DT);
         using T = typename Store<DT>::T;
         using L = typename Lam<LT>::T;
-        const uint64_t cells = (uint64_t)ga.nz * qn * ga.qstride;
+        const uint64_t elems = (uint64_t)ga.nz * qn * ga.qstride;
         const bool planar = planar_ok(ga) && ga.nxy % kBlock == 0 &&
-                            cells * sizeof(T) <= 0xffffffffull && cells * sizeof(L) <= 0xffffffffull;
+                            (!GEN || (elems * sizeof(T) <= 0xffffffffull &&
+                                      elems * sizeof(L) <= 0xffffffffull));
         if (planar && want) {
             LBM_ADJ_LAUNCH(k_adjoint_planar, true);
         } else if (planar) {

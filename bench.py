@@ -323,7 +323,7 @@ def main():
                         "mlups": ncells / (adj_ms * 1e-3) / 1e6},
     }
     dom = "adjoint_f32" if adj_ms >= fwd_ms else "stream_collide_f32"
-    kernel_symbol = {"adjoint_f32": "k_adjoint", "stream_collide_f32": "k_step_tg"}
+    kernel_symbol = {"adjoint_f32": "k_adjoint_planar", "stream_collide_f32": "k_step_tg"}
 
     # plain copy of one state buffer with the library's copy kernel: the
     # achievable-bandwidth reference, and the byte-count reference of the

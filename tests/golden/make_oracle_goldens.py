@@ -15,11 +15,22 @@ file next to this script:
              energy J and its central differences (relative step 1e-4) in
              g_x, omega and along the seeded direction v (seed 10) of the
              initial velocity: c4_duct_fd.json.
+  tube       the 768 x 192 x 192 constricted tube (periodic box, solid where
+             r_cell > 80 (1 - 0.5 exp(-((x - 384)/60)^2))), D3Q19-I TRT
+             (Lambda = 3/16), omega = 1.95, g_x = 2e-6, from rest, T = 500:
+             the outlet flux J (the plane x = nx - 1) and its central
+             differences in g_x (relative step 1e-4) and along the seeded
+             per-cell direction v (seed 11, fluid cells) of the initial
+             velocity (step 1e-6): c5_tube_fd_T500.json.  (The configured
+             horizon is T = 2000; at the oracle's speed a run of it takes
+             hours, so the reference stops at T = 500.)
 
-Usage: python tests/golden/make_oracle_goldens.py shear256|duct [model] [--out DIR]
+Usage: python tests/golden/make_oracle_goldens.py shear256|duct|tube [model] [--out DIR]
 (DIR defaults to this folder.)
 The runs are long (the oracle is plain C): about 15 min per shear-wave model
-and 15 min for the duct on 16 host cores.  Progress goes to stdout.
+and 15 min for the duct on 16 host cores; the tube's five runs take about
+35 min each on 8 cores.  Progress goes to stdout; the tube file is rewritten
+after each run, with "complete" false until the last.
 """
 from __future__ import annotations
 
@@ -128,6 +139,40 @@ def duct():
     _say(f"wrote {out}: {json.dumps(rec)}")
 
 
+def tube():
+    nx, ny, nz, T = 768, 192, 192, 500
+    gx, omega, h, hv = 2e-6, 1.95, 1e-4, 1e-6
+    solid = lbm_inputs.tube_mask(nx, ny, nz, r0=80.0, depth=0.5, centre=384.0, width=60.0)
+    v = lbm_inputs.perturbation((nz, ny, nx), seed=11, amp=1.0) * (solid == 0)
+    u0 = np.zeros((3, nz, ny, nx))
+
+    def J(accel_x, u):
+        cfg = oracle.Config(nx, ny, nz, periodic=(1, 1, 1), improved=1, trt=True, omega=omega,
+                            magic=3.0 / 16.0, accel=(accel_x, 0.0, 0.0), solid=solid)
+        f = _advance(cfg, oracle.init(cfg, u), T, 25, f"tube g={accel_x:.9e}")
+        return oracle.objective(cfg, f, 1)[0]
+
+    rec = {"nx": nx, "ny": ny, "nz": nz, "steps": T, "gx": gx, "omega": omega, "magic": 3 / 16,
+           "h": h, "hv": hv, "objective": "outlet flux: sum of u_x over the fluid cells of x = nx - 1",
+           "mask": "tube_mask(768, 192, 192, r0=80, depth=0.5, centre=384, width=60)",
+           "init": "rest", "direction": "perturbation((192,192,768), seed=11, amp=1) * fluid",
+           "complete": False}
+    out = os.path.join(OUT, "c5_tube_fd_T500.json")
+    runs = [("J", gx, u0), ("J_gx_plus", gx * (1 + h), u0), ("J_gx_minus", gx * (1 - h), u0),
+            ("J_u_plus", gx, hv * v), ("J_u_minus", gx, -hv * v)]
+    for name, a, u in runs:
+        rec[name] = J(a, u)
+        with open(out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        _say(f"{name} = {rec[name]!r}")
+    rec["dJ_dgx"] = (rec["J_gx_plus"] - rec["J_gx_minus"]) / (2 * gx * h)
+    rec["dJ_du_dot_v"] = (rec["J_u_plus"] - rec["J_u_minus"]) / (2 * hv)
+    rec["complete"] = True
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    _say(f"wrote {out}: {json.dumps(rec)}")
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     if "--out" in args:
@@ -141,6 +186,8 @@ if __name__ == "__main__":
             shear256(m)
     elif what == "duct":
         duct()
+    elif what == "tube":
+        tube()
     else:
         print(__doc__)
         sys.exit(2)

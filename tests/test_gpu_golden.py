@@ -12,6 +12,11 @@ the oracle and the seeded input generators):
   oracle's, and the FP32 checkpointed adjoint gradient (g_x, omega and a
   seeded direction of the initial velocity) against the oracle's central
   differences.
+* The 768 x 192 x 192 constricted tube, D3Q19-I TRT, omega = 1.95,
+  g_x = 2e-6, from rest, T = 500: the FP64 GPU outlet flux against the
+  oracle's, and the checkpointed gradient with FP16 forward storage and an
+  FP32 adjoint (g_x and a seeded per-cell direction of the initial
+  velocity) against the oracle's central differences.
 A reference that has not been generated skips its test, with that reason."""
 import json
 import os
@@ -143,3 +148,57 @@ def test_duct_gradient_against_oracle_differences():
     fd = (_fd_run(nx, ny, nz, T, u0, gx * (1 + h), omega)
           - _fd_run(nx, ny, nz, T, u0, gx * (1 - h), omega)) / (2 * gx * h)
     assert abs(fd / ref["dJ_dgx"] - 1) < 1e-6, (fd, ref["dJ_dgx"])
+
+
+def _tube_run(T, u0, gx, omega, solid):
+    from paper_1803_04937_amd import Lattice
+    nz, ny, nx = solid.shape
+    lat = Lattice(nx, ny, nz, u=dev(u0), solid=dev(solid, torch.uint8), periodic=(1, 1, 1),
+                  equilibrium="improved", collision="trt", dtype="f64", omega=omega,
+                  accel=(gx, 0.0, 0.0))
+    lat.step(T)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    lam = lat.new_adjoint(zero=False)
+    lat.objective(1, lat.state, out, lam)
+    J = out[0].item()
+    lat.close()
+    return J
+
+
+def test_tube_gradient_against_oracle_differences():
+    from paper_1803_04937_amd import RolloutConfig, rollout_objective
+    path = os.path.join(GOLDEN, "c5_tube_fd_T500.json")
+    if not os.path.exists(path):
+        pytest.skip("c5_tube_fd_T500.json not generated (tests/golden/make_oracle_goldens.py)")
+    ref = json.load(open(path))
+    if not ref.get("complete"):
+        pytest.skip("c5_tube_fd_T500.json incomplete")
+    nx, ny, nz, T = ref["nx"], ref["ny"], ref["nz"], ref["steps"]
+    gx, omega, h, hv = ref["gx"], ref["omega"], ref["h"], ref["hv"]
+    solid = lbm_inputs.tube_mask(nx, ny, nz, r0=80.0, depth=0.5, centre=384.0, width=60.0)
+    v = lbm_inputs.perturbation((nz, ny, nx), seed=11, amp=1.0) * (solid == 0)
+    u0 = np.zeros((3, nz, ny, nx))
+    # the FP64 GPU objective and its g_x difference against the oracle's
+    J64 = _tube_run(T, u0, gx, omega, solid)
+    fd = (_tube_run(T, u0, gx * (1 + h), omega, solid)
+          - _tube_run(T, u0, gx * (1 - h), omega, solid)) / (2 * gx * h)
+    # FP16 forward storage, FP32 adjoint, ceil(sqrt(T)) checkpoints
+    rc = RolloutConfig(nx, ny, nz, steps=T, periodic=(1, 1, 1), collision="trt", dtype="f16s",
+                       objective=1, solid=dev(solid, torch.uint8))
+    u = dev(u0).requires_grad_(True)
+    a = torch.tensor([gx, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    w = torch.tensor(omega, dtype=torch.float64, requires_grad=True)
+    J16 = rollout_objective(u, a, w, rc)
+    J16.backward()
+    g_u = float((host(u.grad) * v).sum())
+    rel = {"J64": abs(J64 / ref["J"] - 1), "fd64_gx": abs(fd / ref["dJ_dgx"] - 1),
+           "J16": abs(J16.item() / ref["J"] - 1),
+           "gx": abs(a.grad[0].item() / ref["dJ_dgx"] - 1),
+           "u_dir": abs(g_u / ref["dJ_du_dot_v"] - 1)}
+    print("\ntube FP16-forward adjoint vs oracle central differences:",
+          json.dumps({"J_oracle": ref["J"], "J64_gpu": J64, "J16": J16.item(),
+                      "dJ/dgx": [a.grad[0].item(), ref["dJ_dgx"]],
+                      "dJ/du.v": [g_u, ref["dJ_du_dot_v"]], "rel_err": rel}))
+    assert rel["J64"] < 1e-10 and rel["fd64_gx"] < 1e-6
+    assert rel["J16"] < 5e-4
+    assert rel["gx"] < 1e-3 and rel["u_dir"] < 1e-2

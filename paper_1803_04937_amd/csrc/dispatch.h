@@ -46,6 +46,7 @@
     if (gen == kGenOpen) { constexpr int GEN = kGenOpen; BODY; }             \
     else if (gen == kGenWalls) { constexpr int GEN = kGenWalls; BODY; }      \
     else if (gen == kGenWallsPlanar) { constexpr int GEN = kGenWallsPlanar; BODY; } \
+    else if (gen == kGenOpenPlanar) { constexpr int GEN = kGenOpenPlanar; BODY; } \
     else { constexpr int GEN = kGenPeriodic; BODY; }
 
 // Collision operator of the stream-collide kernels (kCo*); MRT and KBC exist

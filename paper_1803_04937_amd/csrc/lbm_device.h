@@ -454,6 +454,8 @@ constexpr int kGenPeriodic = 0, kGenWalls = 1, kGenOpen = 2;
 // the two-grid step then addresses every pull as a uniform plane base plus a
 // 32-bit in-plane offset, as the periodic kernel does.
 constexpr int kGenWallsPlanar = 3;
+// kGenOpenPlanar: the same with open x faces.
+constexpr int kGenOpenPlanar = 4;
 
 // Collision operators of the stream-collide kernels (template parameter CO):
 // SRT / TRT in pair form, MRT (Sec. 3.2), KBC (Sec. 3.3).

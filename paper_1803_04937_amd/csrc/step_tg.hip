@@ -16,17 +16,17 @@ namespace lbm {
 // 2 f^eq+_q(rho_out, u_b), f^eq+ the even part of the equilibrium and u_b the
 // read-out velocity sum c f*(x) - a/2 of the cell's own stored state.  In
 // shifted variables: d_q = -d*_qbar + 2 w_q (rho_out - 1 + E_q(u_b)).
-template <int QN, int DT, int EQ>
+// x, row = z ny + y: the cell's column and row; own(q): the address of the
+// cell's own stored f*_q in src.
+template <int QN, int DT, int EQ, typename Own>
 __device__ __forceinline__ void open_faces(const Geom &g, const Coll<typename Store<DT>::R> &P,
-                                           const typename Store<DT>::T *__restrict__ src,
-                                           const Hood &h, typename Store<DT>::R (&d)[QN]) {
+                                           uint32_t x, uint32_t row, Own own,
+                                           typename Store<DT>::R (&d)[QN]) {
     using S = Store<DT>;
     using R = typename S::R;
     constexpr int NP = (QN - 1) / 2;
-    const uint32_t row = fdiv(h.idx, g.div_nx), x = h.idx - row * g.nx;
     if (x == 0) {
-        const uint32_t z = fdiv(row, g.div_ny), y = row - z * g.ny;
-        const size_t nyz = (size_t)g.ny * g.nz, r = (size_t)z * g.ny + y;
+        const size_t nyz = (size_t)g.ny * g.nz, r = row;
         const R ux = (R)g.inlet[r], uy = (R)g.inlet[nyz + r], uz = (R)g.inlet[2 * nyz + r];
         static_for<QN>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
@@ -39,8 +39,7 @@ __device__ __forceinline__ void open_faces(const Geom &g, const Coll<typename St
         static_for<QN>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             if constexpr (q > 0) {
-                const R v = S::template load<false>(src + q * g.qstride, h.pos, (R)wq(QN, q),
-                                                    P.inv_s);
+                const R v = S::template load<false>(own(q), 0, (R)wq(QN, q), P.inv_s);
                 if constexpr (kC[q].x != 0) jx += R(kC[q].x) * v;
                 if constexpr (kC[q].y != 0) jy += R(kC[q].y) * v;
                 if constexpr (kC[q].z != 0) jz += R(kC[q].z) * v;
@@ -91,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
             else
                 S::template store<H>(o, 0, d[q], (R)wq(QN, q), P.s);
         });
-    } else if constexpr (GEN == kGenWallsPlanar) {
+    } else if constexpr (GEN == kGenWallsPlanar || GEN == kGenOpenPlanar) {
         // walls and / or a mask, every block inside one z-plane (over the
         // active list when there is one): uniform plane bases, 32-bit
         // in-plane offsets; a missing link reads the cell's own opposite slot
@@ -115,6 +114,12 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
             d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(
                 at_bytes(src, (link >> q) & 1u ? pull : self), 0, (R)wq(QN, q), P.inv_s);
         });
+        if constexpr (GEN == kGenOpenPlanar) {
+            const uint32_t y = fdiv(p, g.div_nx);
+            open_faces<QN, DT, EQ>(g, P, p - y * g.nx, z * g.ny + y,
+                                   [&](int q) { return at_bytes(src, (z * QN + q) * qsb + off); },
+                                   d);
+        }
         collide<R, EQ, QN, CO>(d, P);
         SrBits rb{SR ? mix32(idx ^ key) : 0u};
         static_for<QN>([&](auto qc) {
@@ -140,7 +145,11 @@ __global__ __launch_bounds__(kBlock) void k_step_tg(Geom g, Coll<typename Store<
             d[q] = S::template load<fwd_load_hint<NT>(kC[q].x)>(p, fl ? pos : h.pos, (R)wq(QN, q),
                                                                  P.inv_s);
         });
-        if constexpr (GEN == kGenOpen) open_faces<QN, DT, EQ>(g, P, src, h, d);
+        if constexpr (GEN == kGenOpen) {
+            const uint32_t row = fdiv(idx, g.div_nx);
+            open_faces<QN, DT, EQ>(g, P, idx - row * g.nx, row,
+                                   [&](int q) { return src + q * g.qstride + h.pos; }, d);
+        }
         collide<R, EQ, QN, CO>(d, P);
         SrBits rb{SR ? mix32(idx ^ key) : 0u};
         static_for<QN>([&](auto qc) {
@@ -166,8 +175,10 @@ hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, int co, int 
     const uint64_t state_bytes = (uint64_t)g.nz * qn * g.qstride *
                                  (dtype == LBM_F64 ? 8 : dtype == LBM_F16_SHIFTED ||
                                   dtype == LBM_BF16_SHIFTED ? 2 : 4);
-    if (gen == kGenWalls && planar_ok(g) && g.nxy % kBlock == 0 && state_bytes <= 0xffffffffull)
-        gen = kGenWallsPlanar;
+    if (planar_ok(g) && g.nxy % kBlock == 0 && state_bytes <= 0xffffffffull) {
+        if (gen == kGenWalls) gen = kGenWallsPlanar;
+        if (gen == kGenOpen) gen = kGenOpenPlanar;
+    }
     const dim3 grid = gen != kGenPeriodic ? dim3(gen_blocks(g)) : plane_grid(g), block(kBlock);
     if (grid.x == 0) return hipSuccess;   // every cell solid
     LBM_DISPATCH_DT(dtype, LBM_DISPATCH_EQ(eq, LBM_DISPATCH_GEN3(gen, LBM_DISPATCH_CO(

@@ -100,17 +100,25 @@ COLLS = [("srt", {}), ("trt", dict(trt=True)), ("mrt", dict(mrt=True, omega3=1.5
          ("kbc", dict(kbc=True))]
 
 
+# (nx, ny, nz, mask): the general kernel (planes of 84 cells) and the planar
+# one (planes of whole 256-cell blocks), with a mask and with walls alone
+OPEN_SHAPES = [(12, 7, 5, True), (32, 8, 5, True), (64, 12, 3, False)]
+
+
 @pytest.mark.parametrize("coll,ckw", COLLS, ids=[c[0] for c in COLLS])
 @pytest.mark.parametrize("improved", [0, 1, 2])
 @pytest.mark.parametrize("stencil", [19, 27])
-def test_open_faces_fp64(coll, ckw, improved, stencil):
+@pytest.mark.parametrize("shape", OPEN_SHAPES, ids=["general", "planar_mask", "planar_walls"])
+def test_open_faces_fp64(coll, ckw, improved, stencil, shape):
     if stencil == 27 and coll in ("mrt", "kbc"):
         pytest.skip("MRT and KBC are D3Q19 only")
     if stencil == 27 and improved:
         pytest.skip("D3Q27 has one equilibrium")
-    nx, ny, nz = 12, 7, 5
-    solid = random_blobs((nz, ny, nx), 7)
-    solid[:, :, 0] = 0
+    nx, ny, nz, mask = shape
+    solid = None
+    if mask:
+        solid = random_blobs((nz, ny, nx), 7)
+        solid[:, :, 0] = 0
     rng = np.random.default_rng(8)
     inlet = rng.uniform(-0.02, 0.04, (3, nz, ny))
     cfg = oracle.Config(nx, ny, nz, periodic=(0, 0, 1), improved=improved, omega=1.6,
@@ -129,8 +137,9 @@ def test_open_faces_fp64(coll, ckw, improved, stencil):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f32s", "f16s", "bf16s"])
-def test_open_faces_reduced_one_step(dtype):
-    nx, ny, nz = 20, 9, 6
+@pytest.mark.parametrize("shape", [(20, 9, 6), (64, 8, 6)], ids=["general", "planar"])
+def test_open_faces_reduced_one_step(dtype, shape):
+    nx, ny, nz = shape
     rng = np.random.default_rng(10)
     inlet = np.zeros((3, nz, ny))
     inlet[0] = 0.03

@@ -450,9 +450,10 @@ constexpr int kSolidBit = 31;
 // x = nx - 1/2.
 constexpr int kGenPeriodic = 0, kGenWalls = 1, kGenOpen = 2;
 // kGenWallsPlanar: walls and / or a mask on a lattice whose planes hold a
-// whole number of 256-cell blocks, so that each block lies in one z-plane:
-// the two-grid step then addresses every pull as a uniform plane base plus a
-// 32-bit in-plane offset, as the periodic kernel does.
+// whole number of 256-cell blocks, so that each block lies in one z-plane,
+// and whose state spans less than 4 GiB: the two-grid step then addresses
+// every pull and every bounce-back slot as a 32-bit byte offset from the
+// state's base, the plane term uniform over the block.
 constexpr int kGenWallsPlanar = 3;
 // kGenOpenPlanar: the same with open x faces.
 constexpr int kGenOpenPlanar = 4;

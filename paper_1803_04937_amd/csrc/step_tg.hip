@@ -169,8 +169,9 @@ hipError_t launch_step_tg(const Geom &g, int qn, int dtype, int eq, int co, int 
                           void *dst, hipStream_t st) {
     // kGenPeriodic runs the planar launch; lattices it cannot address take the
     // general kernel, which is exact for periodic lattices without a mask too.
-    // Walls and masks take the planar addressing when every 256-cell block
-    // lies inside one plane.
+    // Walls, masks and open faces take the planar addressing when every
+    // 256-cell block lies inside one plane and the state spans less than
+    // 4 GiB (its byte offsets then fit 32 bits).
     if (gen == kGenPeriodic && !planar_ok(g)) gen = kGenWalls;
     const uint64_t state_bytes = (uint64_t)g.nz * qn * g.qstride *
                                  (dtype == LBM_F64 ? 8 : dtype == LBM_F16_SHIFTED ||

@@ -208,15 +208,24 @@ __global__ __launch_bounds__(kBlock) LBM_ADJ_OCCUPANCY void k_adjoint_planar(
     const bool fluid = !link_solid(link);
     constexpr bool HL = NT && LBM_NT_ADJ_LOADS != 0, HS = NT && LBM_NT_ADJ_STORES != 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // the cell's own lambda does not depend on its link word: with walls or
+    // a mask these loads are issued before the word is waited for (solid
+    // cells of the block load it too)
+    R lam[QN];
+    if constexpr (GEN)
+        static_for<QN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            lam[q] = (R)ld<HL>(plane_at<GEN, QN>(lam_next, g, z, q, p * LB));
+        });
     if (fluid) {
         const PlaneHood h = make_plane_hood(p, z, g);
-        R d[QN], lam[QN];
+        R d[QN];
         static_for<QN>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             const bool fl = !GEN || ((link >> q) & 1u);
             d[q] = S::template load<HL>(pull_or_own<GEN, QN, q>(state, g, h, z, fl), 0,
                                         (R)wq(QN, q), P.inv_s);
-            lam[q] = (R)ld<HL>(plane_at<GEN, QN>(lam_next, g, z, q, p * LB));
+            if constexpr (!GEN) lam[q] = (R)ld<HL>(plane_at<GEN, QN>(lam_next, g, z, q, p * LB));
         });
         adjoint_cell<R, EQ, QN, MRT>(d, lam, P, acc);
         static_for<QN>([&](auto qc) {

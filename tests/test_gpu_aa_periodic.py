@@ -16,12 +16,14 @@ SHAPES = [(300, 4, 5), (64, 8, 6), (33, 18, 14), (256, 3, 4), (16, 5, 3)]
 SHAPE_IDS = ["rows300", "rows64", "33x18x14", "rows256", "16x5x3"]
 
 
-@pytest.mark.parametrize("rounding", ["nearest", "stochastic"])
-@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s", "bf16s"])
+# stochastic rounding applies to the 16-bit formats only
+STORAGE = [("f64", "nearest"), ("f32", "nearest"), ("f32s", "nearest"), ("f16s", "nearest"),
+           ("bf16s", "nearest"), ("f16s", "stochastic"), ("bf16s", "stochastic")]
+
+
+@pytest.mark.parametrize("dtype,rounding", STORAGE, ids=[f"{d}-{r}" for d, r in STORAGE])
 @pytest.mark.parametrize("si", range(len(SHAPES)), ids=SHAPE_IDS)
 def test_aa_periodic_equals_two_grid_bitwise(si, dtype, rounding):
-    if rounding == "stochastic" and dtype not in ("f16s", "bf16s"):
-        pytest.skip("stochastic rounding applies to the 16-bit formats")
     nx, ny, nz = SHAPES[si]
     cfg, kw = case(nx, ny, nz, trt=True, omega=1.9, accel=(1e-5, -2e-6, 3e-6))
     u0 = lbm_inputs.shear_waves(cfg.shape, seed=17 + si, amax=0.05)

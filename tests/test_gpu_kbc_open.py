@@ -105,15 +105,17 @@ COLLS = [("srt", {}), ("trt", dict(trt=True)), ("mrt", dict(mrt=True, omega3=1.5
 OPEN_SHAPES = [(12, 7, 5, True), (32, 8, 5, True), (64, 12, 3, False)]
 
 
-@pytest.mark.parametrize("coll,ckw", COLLS, ids=[c[0] for c in COLLS])
-@pytest.mark.parametrize("improved", [0, 1, 2])
-@pytest.mark.parametrize("stencil", [19, 27])
+# D3Q19: every collision and equilibrium; D3Q27 (one equilibrium, no MRT or
+# KBC): SRT and TRT
+OPEN_MODELS = ([(19, improved, c) for improved in (0, 1, 2) for c in range(len(COLLS))]
+               + [(27, 0, 0), (27, 0, 1)])
+
+
+@pytest.mark.parametrize("stencil,improved,ci", OPEN_MODELS,
+                         ids=[f"q{q}-eq{e}-{COLLS[c][0]}" for q, e, c in OPEN_MODELS])
 @pytest.mark.parametrize("shape", OPEN_SHAPES, ids=["general", "planar_mask", "planar_walls"])
-def test_open_faces_fp64(coll, ckw, improved, stencil, shape):
-    if stencil == 27 and coll in ("mrt", "kbc"):
-        pytest.skip("MRT and KBC are D3Q19 only")
-    if stencil == 27 and improved:
-        pytest.skip("D3Q27 has one equilibrium")
+def test_open_faces_fp64(stencil, improved, ci, shape):
+    coll, ckw = COLLS[ci]
     nx, ny, nz, mask = shape
     solid = None
     if mask:

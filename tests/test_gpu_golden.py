@@ -49,9 +49,10 @@ def test_shear256_fp64_1000_steps(model, pattern):
     1e-12 bound, ten times the spread that a 1e-15 relative perturbation of
     the initial state shows after the same 1000 GPU steps: D3Q19-I TRT at
     omega = 1.95 (omega_minus = 0.066 at Lambda = 3/16) amplifies
-    perturbations of this field about 1.8 % per step (1e-15 grows to ~1e-7),
-    so the rounding differences of any two correct implementations grow
-    alike; D3Q19-S SRT does not amplify them and keeps the plain bound."""
+    perturbations of this field (a relative 1e-15 perturbation of the
+    initial PDFs leaves the run ~2e-10 away after 1000 steps), so the
+    rounding differences of any two correct implementations grow alike;
+    D3Q19-S SRT does not amplify them and keeps the plain bound."""
     import oracle
     from paper_1803_04937_amd import Lattice
     z = _npz(f"c2_256_w195_{model}.npz")

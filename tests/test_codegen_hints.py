@@ -6,7 +6,10 @@ take their hints as template parameters.  This test compiles the kernel
 sources to gfx950 assembly with the library's own flags and counts the `nt`
 cache-policy bits of every stream-collide and adjoint instantiation:
   streaming forward (NT = 1): the 9 loads with c_x = 0 (all loads in the AA
-      local step, which reads its own slots) and every store;
+      local step, which reads its own slots) and every store (the periodic
+      AA neighbour step of the 4-byte formats has two store sites for each
+      direction with c_x != 0: the aligned store of a value parked in LDS
+      and the direct store of one whose target lies outside the block);
   cached forward (NT = 0): none;
   streaming adjoint: every PDF and lambda load and every lambda store;
   cached adjoint: none.
@@ -21,8 +24,8 @@ import pytest
 
 from paper_1803_04937_amd import build as B
 
-KERNEL = re.compile(r'^(_ZN3lbm\d+(k_step_tg|k_step_aa_nb|k_step_aa_loc|k_adjoint)I\S*?)'
-                    r'EEEvNS\S*:\s', re.M)
+KERNEL = re.compile(r'^(_ZN3lbm\d+(k_step_tg|k_step_aa_nb|k_step_aa_loc|k_adjoint_planar|'
+                    r'k_adjoint)I\S*?)EEEvNS\S*:\s', re.M)
 
 
 @pytest.fixture(scope="module")
@@ -59,6 +62,10 @@ def test_forward_hints(assembly):
         qn = int(qn)
         want_l = 0 if nt == "0" else (qn if kind == "k_step_aa_loc" else 9)
         want_s = 0 if nt == "0" else qn
+        if kind == "k_step_aa_nb" and nt == "1":
+            dt, gen = re.search(r"ILi\d+ELi(\d)ELi\dELb([01])", name).groups()
+            if gen == "0" and dt in ("1", "2"):     # FP32, shifted FP32: parked
+                want_s += 10 if qn == 19 else 18
         assert (nl, ns) == (want_l, want_s), (name, nl, ns)
         seen += 1
     assert seen > 500, seen
@@ -67,7 +74,9 @@ def test_forward_hints(assembly):
 def test_adjoint_hints(assembly):
     asm = assembly["adjoint.hip"]
     seen = 0
-    for name, _, nl, ns, n_loads, _ in _counts(asm):
+    kinds = set()
+    for name, kind, nl, ns, n_loads, _ in _counts(asm):
+        kinds.add(kind)
         qn = int(re.search(r"ILi(\d+)E", name).group(1))
         gen = re.search(r"ILi\d+ELi\dELi\dELi\dELb([01])", name).group(1) == "1"
         if name.endswith("Lb0"):          # cached policy: no hint at all
@@ -86,6 +95,7 @@ def test_adjoint_hints(assembly):
             assert nl == n_loads and ns == qn + nxs, (name, nl, n_loads, ns)
         seen += 1
     assert seen > 100, seen
+    assert kinds == {"k_adjoint", "k_adjoint_planar"}, kinds
 
 
 def test_no_packed_fp32(assembly):

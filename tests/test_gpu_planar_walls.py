@@ -68,3 +68,26 @@ def test_planar_walls_equal_aa_bitwise(dtype, rounding):
         np.testing.assert_array_equal(host(a.get_pdfs()), host(b.get_pdfs()))
     a.close()
     b.close()
+
+
+def test_walls_state_over_4gib_takes_the_general_kernel():
+    """Walls on a lattice whose planes hold whole blocks but whose FP64 state
+    spans more than 4 GiB (1024 x 512 x 56 cells, 4.46 GB): the 32-bit
+    offsets of the planar kernel would not reach it, so the step takes the
+    general kernel.  Sampled cells after one step against the oracle's
+    per-cell step, including the wall rows and the last plane."""
+    nx, ny, nz = 1024, 512, 56
+    assert nx * ny % 256 == 0 and nx * ny * nz * 19 * 8 > 2 ** 32
+    cfg, kw = case(nx, ny, nz, periodic=(1, 0, 1), trt=True, omega=1.7, accel=(1e-4, 0, 0))
+    u0 = lbm_inputs.perturbation(cfg.shape, seed=41, amp=0.05)
+    lat = lattice(cfg, kw, u0, dtype="f64")
+    f0 = oracle.init(cfg, u0)
+    del u0
+    rng = np.random.default_rng(42)
+    cells = rng.choice(nx * ny * nz, size=400, replace=False)
+    edge = [(z * ny + y) * nx + x for z in (0, nz - 1) for y in (0, ny - 1) for x in (0, nx - 1)]
+    cells = np.unique(np.concatenate([cells, edge])).astype(np.int64)
+    lat.step(1)
+    got = host(lat.sample_pdfs(cells))
+    lat.close()
+    assert_f64_parity(got.T, oracle.step_cells(cfg, f0, cells).T, "walls over 4 GiB")

@@ -149,7 +149,7 @@ typedef struct {
     int32_t periodic[3];      /* per axis: 1 periodic, 0 half-way bounce-back walls
                                  at both faces (Sec. 5.1)                        */
     int32_t equilibrium;      /* LBM_EQ_*                                         */
-    int32_t collision;        /* LBM_SRT / LBM_TRT / LBM_MRT                      */
+    int32_t collision;        /* LBM_SRT / LBM_TRT / LBM_MRT / LBM_KBC (D3Q19)    */
     int32_t dtype;            /* storage, LBM_F64 ... LBM_BF16_SHIFTED             */
     int32_t pattern;          /* LBM_TWO_GRID / LBM_AA                            */
     int32_t compressible;     /* 0: rho0 = 1 (the paper's choice); 1: rho0 = rho   */

@@ -12,11 +12,13 @@ from _helpers import assert_adjoint_parity, case, dev, host, lattice, random_blo
 pytestmark = pytest.mark.gpu
 
 # (nx, ny, nz), periodic, with a mask
+# 64x16x19: 76 blocks, two whole groups of 32 taken four per XCD and a
+# tail of 12 in dispatch order
 SHAPES = [((32, 16, 12), (1, 0, 1), True), ((64, 4, 5), (0, 1, 1), False),
           ((16, 32, 7), (1, 1, 1), False), ((256, 2, 3), (1, 1, 1), True),
-          ((512, 1, 3), (0, 1, 1), True)]
+          ((512, 1, 3), (0, 1, 1), True), ((64, 16, 19), (1, 0, 1), True)]
 SHAPE_IDS = ["32x16x12_mask", "64x4x5_walls", "16x32x7_periodic", "256x2x3_mask",
-             "512x1x3_mask"]
+             "512x1x3_mask", "64x16x19_mask"]
 MODELS = [dict(improved=0), dict(improved=1, trt=True), dict(improved=2, trt=True),
           dict(improved=1, mrt=(1.6, 1.1))]
 MODEL_IDS = ["S-SRT", "I-TRT", "I3-TRT", "I-MRT"]

@@ -12,11 +12,14 @@ from _helpers import assert_f64_parity, case, dev, host, lattice, random_blobs
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [((32, 16, 12), (1, 0, 1)), ((64, 4, 5), (0, 1, 1)), ((16, 32, 7), (1, 1, 0))]
+# the last shape has 76 blocks: two whole groups of 32 taken four per XCD
+# and a tail of 12 in dispatch order
+SHAPES = [((32, 16, 12), (1, 0, 1)), ((64, 4, 5), (0, 1, 1)), ((16, 32, 7), (1, 1, 0)),
+          ((64, 16, 19), (1, 0, 1))]
 COLL = [dict(trt=False), dict(trt=True), dict(mrt=(1.6, 1.1))]
 
 
-@pytest.mark.parametrize("shape,per", SHAPES, ids=["32x16x12", "64x4x5", "16x32x7"])
+@pytest.mark.parametrize("shape,per", SHAPES, ids=["32x16x12", "64x4x5", "16x32x7", "64x16x19"])
 @pytest.mark.parametrize("improved", [0, 1, 2])
 @pytest.mark.parametrize("ci", range(len(COLL)), ids=["srt", "trt", "mrt"])
 def test_planar_walls_fp64(shape, per, improved, ci):
